@@ -1,0 +1,157 @@
+"""CPU FP64 oracle for event-by-event oscillation reweighting.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark load this package.  It wraps
+``liboscoracle.so`` (plain C, see ``osc_oracle.c``) with ctypes and shares
+no code with the GPU library.
+
+Parameter sets are passed as a mapping with the keys
+``sin2_th12, sin2_th23, sin2_th13, dm2_32, dm2_21, delta_cp`` or as a
+sequence in that order.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB as _LIB_PATH
+
+_FIELDS = ("sin2_th12", "sin2_th23", "sin2_th13", "dm2_32", "dm2_21", "delta_cp")
+
+# tile reduction contract of the binned PDF: W lanes x K events per lane
+CONTRACT_W = 64
+CONTRACT_K = 16
+
+
+class OracleParams(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in _FIELDS]
+
+
+def to_params(p) -> OracleParams:
+    if isinstance(p, OracleParams):
+        return p
+    if hasattr(p, "keys"):
+        return OracleParams(*[float(p[f]) for f in _FIELDS])
+    if hasattr(p, "sin2_th12"):
+        return OracleParams(*[float(getattr(p, f)) for f in _FIELDS])
+    vals = [float(v) for v in p]
+    if len(vals) != 6:
+        raise ValueError("a parameter set has six values")
+    return OracleParams(*vals)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"oracle library not built: {_LIB_PATH} "
+                               "(run __graft_entry__.build() or oracle/build.py)")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER(OracleParams)
+        d, i32, i64 = ctypes.c_double, ctypes.c_int32, ctypes.c_int64
+        vp = ctypes.c_void_p
+        L.oracle_k_phase.restype = d
+        L.oracle_k_matter.restype = d
+        L.oracle_pmns.argtypes = [P, ctypes.c_int, vp]
+        L.oracle_prob_vacuum.argtypes = [P, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_prob_vacuum.restype = d
+        L.oracle_prob.argtypes = [P, d, d, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.oracle_prob.restype = d
+        L.oracle_prob_batch.argtypes = [P, d, d, d, i64, vp, vp, vp]
+        L.oracle_prob_batch.restype = ctypes.c_int
+        L.oracle_bin_index.argtypes = [d, d, d, i32]
+        L.oracle_bin_index.restype = i32
+        L.oracle_hist_contract.argtypes = [vp, vp, i64, i32, i32, i32, vp]
+        L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, i32, i32, vp, vp]
+        L.oracle_fill_pdf.restype = ctypes.c_int
+        L.oracle_num_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def k_phase() -> float:
+    return lib().oracle_k_phase()
+
+
+def k_matter() -> float:
+    return lib().oracle_k_matter()
+
+
+def num_threads() -> int:
+    return lib().oracle_num_threads()
+
+
+def pmns(params, anti=False) -> np.ndarray:
+    out = np.zeros(18, dtype=np.float64)
+    pp = to_params(params)
+    lib().oracle_pmns(ctypes.byref(pp), int(bool(anti)), _ptr(out))
+    return (out[0::2] + 1j * out[1::2]).reshape(3, 3)
+
+
+def prob_vacuum(params, L_km, E, alpha, beta, anti=False) -> float:
+    pp = to_params(params)
+    return lib().oracle_prob_vacuum(ctypes.byref(pp), float(L_km), float(E),
+                                    int(alpha), int(beta), int(bool(anti)))
+
+
+def prob(params, L_km, rho, Ye, E, alpha, beta, anti=False) -> float:
+    pp = to_params(params)
+    return lib().oracle_prob(ctypes.byref(pp), float(L_km), float(rho), float(Ye),
+                             float(E), int(alpha), int(beta), int(bool(anti)))
+
+
+def prob_batch(params, L_km, rho, Ye, e_true, flags) -> np.ndarray:
+    e = np.ascontiguousarray(e_true, dtype=np.float64)
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    if e.shape != f.shape:
+        raise ValueError("e_true and flags differ in length")
+    out = np.empty_like(e)
+    pp = to_params(params)
+    lib().oracle_prob_batch(ctypes.byref(pp), float(L_km), float(rho), float(Ye),
+                            e.size, _ptr(e), _ptr(f), _ptr(out))
+    return out
+
+
+def bin_index(x, lo, hi, nbins) -> int:
+    return lib().oracle_bin_index(float(x), float(lo), float(hi), int(nbins))
+
+
+def bin_indices(x, lo, hi, nbins) -> np.ndarray:
+    return np.array([bin_index(v, lo, hi, nbins) for v in np.asarray(x, dtype=np.float64)],
+                    dtype=np.int32)
+
+
+def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K) -> np.ndarray:
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    b = np.ascontiguousarray(bins, dtype=np.int32)
+    if c.shape != b.shape:
+        raise ValueError("c and bins differ in length")
+    if b.size and (b.min() < 0 or b.max() >= nbt):
+        raise ValueError("bin index out of range")
+    out = np.zeros(int(nbt), dtype=np.float64)
+    lib().oracle_hist_contract(_ptr(c), _ptr(b), c.size, int(nbt), int(W), int(K), _ptr(out))
+    return out
+
+
+def fill_pdf(params, L_km, rho, Ye, e_true, flags, weight, e_reco, nbins, lo, hi,
+             W=CONTRACT_W, K=CONTRACT_K, want_p=True):
+    e = np.ascontiguousarray(e_true, dtype=np.float64)
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    r = np.ascontiguousarray(e_reco, dtype=np.float64)
+    if not (e.shape == f.shape == w.shape == r.shape):
+        raise ValueError("event arrays differ in length")
+    hist = np.zeros(int(nbins) + 2, dtype=np.float64)
+    p = np.empty_like(e) if want_p else None
+    pp = to_params(params)
+    lib().oracle_fill_pdf(ctypes.byref(pp), float(L_km), float(rho), float(Ye), e.size,
+                          _ptr(e), _ptr(f), _ptr(w), _ptr(r), int(nbins), float(lo), float(hi),
+                          int(W), int(K), _ptr(hist), _ptr(p) if p is not None else ctypes.c_void_p(0))
+    return hist, p

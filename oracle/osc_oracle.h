@@ -1,0 +1,103 @@
+/*
+ * osc_oracle.h -- CPU FP64 oracle for event-by-event oscillation reweighting.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that tests, the smoke
+ * check and the CPU-baseline timing can compare the GPU library against a
+ * plain, slow, obviously correct implementation written from the paper
+ * (arXiv:1311.7579, "Accelerated Event-by-Event Neutrino Oscillation
+ * Reweighting with Matter Effects on a GPU").  Product code never links,
+ * loads or calls it.  It shares no source with the GPU library.
+ *
+ * Conventions (identical meaning to the product's public header, written
+ * independently):
+ *   flavour index 0 = e, 1 = mu, 2 = tau;
+ *   energies in GeV, baseline in km, mass splittings in eV^2,
+ *   density in g/cm^3, Ye = electrons per nucleon.
+ *   Event flag byte: bits 0-1 initial flavour alpha, bits 2-3 final flavour
+ *   beta, bit 4 antineutrino.
+ *   Histogram layout: nbins regular bins, then underflow, then overflow.
+ */
+#ifndef OSC_ORACLE_H
+#define OSC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The six oscillation parameters of Table 1 (sin^2 of the three mixing
+ * angles, the two mass splittings, the CP phase in radians). */
+typedef struct {
+    double sin2_th12, sin2_th23, sin2_th13;
+    double dm2_32, dm2_21;
+    double delta_cp;
+} oracle_params;
+
+/* Phase constant: the vacuum phase m^2 L / (2E) in natural units equals
+ * oracle_k_phase() * m^2[eV^2] * L[km] / E[GeV]. */
+double oracle_k_phase(void);
+
+/* Matter constant: 2 sqrt(2) G_F N_e E equals
+ * oracle_k_matter() * Ye * rho[g/cm^3] * E[GeV]  (eV^2). */
+double oracle_k_matter(void);
+
+/* PMNS matrix (PDG parameterisation) as interleaved re/im, row = flavour,
+ * column = mass state: out[2*(3*a+i)] = Re U_ai, out[2*(3*a+i)+1] = Im U_ai.
+ * anti != 0 returns the complex conjugate (antineutrino rule). */
+void oracle_pmns(const oracle_params* p, int anti, double* out);
+
+/* Sec. 1.1, Eq. (1) in corrected form: vacuum transition probability
+ * P(alpha -> beta) = |sum_i conj(U_alpha i) U_beta i exp(-i k m_i^2 L/E)|^2. */
+double oracle_prob_vacuum(const oracle_params* p, double L_km, double E,
+                          int alpha, int beta, int anti);
+
+/* Sec. 1.1 and 2.1: probability through constant-density matter via the
+ * matter-modified mass matrix, its analytic characteristic-cubic
+ * eigenvalues and the projector expansion of the evolution operator.
+ * rho may be negative (test hook: flips the sign of the matter term
+ * independently of the antineutrino flag). */
+double oracle_prob(const oracle_params* p, double L_km, double rho, double Ye,
+                   double E, int alpha, int beta, int anti);
+
+/* Same as oracle_prob for arrays of events described by flag bytes.
+ * OpenMP-parallel over events; returns the thread count used. */
+int oracle_prob_batch(const oracle_params* p, double L_km, double rho, double Ye,
+                      int64_t n, const double* e_true, const uint8_t* flags,
+                      double* p_out);
+
+/* Bin index of one reconstructed energy: q = (x - lo) / wb with
+ * wb = (hi - lo) / nbins, both IEEE FP64 operations; q < 0 -> nbins
+ * (underflow), q >= nbins or NaN -> nbins + 1 (overflow), else floor(q). */
+int32_t oracle_bin_index(double x, double lo, double hi, int32_t nbins);
+
+/* Deterministic histogram of contributions c[i] into bin[i] (values in
+ * [0, nbt)) following the tile reduction contract with tile width W lanes
+ * and K events per lane (both powers of two):
+ *   tile t holds events t*W*K .. t*W*K + W*K - 1; lane l of the tile takes
+ *   events t*W*K + m*W + l for m = 0..K-1 and sums them in ascending m,
+ *   starting from +0.0, into a private per-bin accumulator;
+ *   for each bin, the W lane sums of a tile are added by the complete
+ *   binary tree over lane index (adjacent pairs first);
+ *   for each bin, the tile results are added by the complete binary tree
+ *   over tile index, padded with +0.0 to a power of two.
+ * out has nbt entries. */
+void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
+                          int32_t nbt, int32_t W, int32_t K, double* out);
+
+/* Plain reweight + binned PDF (Sec. 1.1.1): P per event, contribution
+ * c = w * P (separately rounded), bin of e_reco, histogram by the tile
+ * contract above.  hist_out has nbins + 2 entries; p_out may be NULL. */
+int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
+                    int64_t n, const double* e_true, const uint8_t* flags,
+                    const double* weight, const double* e_reco,
+                    int32_t nbins, double lo, double hi, int32_t W, int32_t K,
+                    double* hist_out, double* p_out);
+
+/* OpenMP thread count the batch functions use. */
+int oracle_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
