@@ -1,0 +1,164 @@
+"""Throughput and latency of the plain FP64 reweight + binned PDF on one GPU.
+
+Workload: 1e7 synthetic Monte Carlo events (true E log-uniform on
+[0.1, 10] GeV, nu_mu -> nu_mu / nu_mu -> nu_e at 50 % each, 20 %
+antineutrinos, weights U(0.5, 1.5), reco E = true E x N(1, 0.1)), Table 1
+parameters, 295 km at 2.6 g/cm^3, 50 reco-E bins on [0, 3] GeV, per-event
+P written out.  One step = one osc_fill_pdf call on the resident sample.
+
+Prints one JSON line: evals/s over the timed steps, p50/p99 latency of
+single calls measured on the host (launch to histogram on the host), the
+roofline position of the per-event kernel timed with hipEvents on its own
+stream, and the CPU oracle timed on a bounded slice of the same events.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_EVENTS = 10_000_000
+SEED = 1
+NBINS, LO, HI = 50, 0.0, 3.0
+
+# Algorithmic HBM bytes per event of the fused kernel: read E (8), flags (1),
+# weight (8), reco E (8); write P (8).  Histogram partials add
+# (nbins + 2) * 8 B per 1024-event tile (0.4 B/event) and are left out.
+BYTES_PER_EVENT = 33
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--latency-calls", type=int, default=1000)
+    ap.add_argument("--cpu-events", type=int, default=2_000_000,
+                    help="events of the oracle's timed slice (all host threads)")
+    ap.add_argument("--cpu-events-1t", type=int, default=200_000,
+                    help="events of the oracle's single-thread slice")
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(sample, n_all, n_one):
+    import numpy as np
+    import oracle
+    from paper_1311_7579_amd import workload
+
+    def run(n):
+        t0 = time.perf_counter()
+        oracle.fill_pdf(workload.TABLE1, sample.L_km, sample.rho_gcc, sample.Ye,
+                        sample.e_true[:n], sample.flags[:n], sample.weight[:n],
+                        sample.e_reco[:n], NBINS, LO, HI, want_p=True)
+        return time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    t_all = run(n_all)
+    oracle.set_num_threads(1)
+    t_one = run(n_one)
+    oracle.set_num_threads(threads)
+    return {
+        "value": n_all / t_all, "unit": "evals/s", "cores": threads, "kind": "oracle",
+        "sample": f"first {n_all} events of the 1e7-event workload, {threads} OpenMP threads "
+                  f"({t_all:.2f} s wall)",
+        "single_core_value": n_one / t_one,
+        "single_core_sample": f"first {n_one} events, 1 thread ({t_one:.2f} s)",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards by events or parameter sets, see the design notes)", flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1311_7579_amd import osc, workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", flush=True)
+        sys.exit(1)
+
+    s = workload.make_sample(N_EVENTS, SEED)
+    ctx = osc.Context(0)
+    ctx.osc_set_params([workload.TABLE1])
+    ds = osc.DeviceSample.from_host(s)
+    hist = torch.empty(NBINS + 2, dtype=torch.float64, device="cuda")
+    p_out = torch.empty(N_EVENTS, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.osc_fill_pdf(ds, 0, NBINS, LO, HI, hist, p_out, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = N_EVENTS / (ms_per_step * 1e-3)
+
+    # per-kernel device time with hipEvents recorded on the launch stream
+    ctx.osc_profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
+    ctx.osc_profile_enable(False)
+    kernel_ms = ev_ms / max(ev_n, 1)
+    merge_avg_ms = merge_ms / max(merge_n, 1)
+
+    # end-to-end latency of single calls: launch -> histogram on the host
+    lat = []
+    host_hist = torch.empty(NBINS + 2, dtype=torch.float64, pin_memory=True)
+    for _ in range(args.latency_calls):
+        a = time.perf_counter()
+        step()
+        host_hist.copy_(hist, non_blocking=False)
+        lat.append(time.perf_counter() - a)
+    lat = np.array(lat) * 1e3
+
+    achieved_gbs = BYTES_PER_EVENT * N_EVENTS / (kernel_ms * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
+        "kernel": "tile_kernel<kPdf, write P>", "kernel_ms": kernel_ms,
+        "merge_kernel_ms": merge_avg_ms,
+        "algorithmic_bytes_per_event": BYTES_PER_EVENT,
+    }
+
+    result = {
+        "metric": "oscillation-prob evals/sec (events x param sets) at 1 GPU + p50/p99 reweight latency",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "plain FP64 reweight + 50-bin reco-E PDF, 1e7 events x 1 parameter "
+                               "set (Table 1, 295 km, 2.6 g/cm^3), per-event P written",
+                   "events": N_EVENTS, "param_sets": 1, "nbins": NBINS, "range_GeV": [LO, HI],
+                   "seed": SEED, "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "calls": args.latency_calls},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(s, args.cpu_events, args.cpu_events_1t)
+        result["speedup_vs_cpu_all_cores"] = value / result["cpu_baseline"]["value"]
+        result["speedup_vs_cpu_one_core"] = value / result["cpu_baseline"]["single_core_value"]
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

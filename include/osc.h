@@ -1,0 +1,172 @@
+/*
+ * osc.h -- C ABI of libosc: event-by-event three-flavour neutrino
+ * oscillation reweighting through constant-density matter on AMD MI355X
+ * (gfx950), after arXiv:1311.7579.
+ *
+ * The operation (Sec. 1.1, 1.1.1, 2.1 of the paper): for every Monte Carlo
+ * event with true energy E, initial flavour alpha, final flavour beta and a
+ * neutrino / antineutrino flag, compute the oscillation probability
+ * P(alpha -> beta) over a baseline L through matter of constant density
+ * (matter effects on nu_e from forward scattering on electrons), in double
+ * precision; then weight the event by w * P and fill a binned
+ * reconstructed-energy PDF.  Parameter-only quantities are computed on the
+ * host (Sec. 2.1) and the per-event work runs in HIP kernels.
+ *
+ * Units: E in GeV, L in km, mass splittings in eV^2, density in g/cm^3,
+ * Ye = electrons per nucleon.  Flavour index 0 = e, 1 = mu, 2 = tau.
+ *
+ * Execution model: every call that takes a stream enqueues its kernels on
+ * that stream (a hipStream_t passed as void*, NULL = the null stream) and
+ * returns before they finish; results are valid once the stream has
+ * synchronised.  All device pointers are caller-owned device memory (for
+ * example torch tensors' data pointers) and must stay alive until then.
+ * Errors are reported as status codes; nothing aborts the process.
+ */
+#ifndef OSC_H
+#define OSC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OSC_OK = 0,
+    OSC_ERR_INVALID_ARG = 1,   /* a NULL pointer, a value outside its domain */
+    OSC_ERR_OUT_OF_MEMORY = 2, /* device scratch could not be allocated      */
+    OSC_ERR_DEVICE = 3,        /* no usable GPU, or a HIP runtime failure     */
+    OSC_ERR_BUDGET = 4,        /* reserved: over a memory budget              */
+    OSC_ERR_NOT_READY = 5      /* reserved: result not available yet          */
+} osc_status;
+
+typedef enum {
+    OSC_FP64 = 0,        /* every step in FP64 (the paper's precision, Sec. 2.1) */
+    OSC_FP32_MIXED = 1   /* FP64 eigenvalues and phases, FP32 amplitude assembly  */
+} osc_precision;
+
+/* Opaque context bound to one device: holds the parameter sets and the
+ * device scratch used by the histogram reduction. */
+typedef struct osc_ctx osc_ctx;
+
+/* One oscillation parameter set: the six rows of Table 1.
+ * sin2_th12, sin2_th23, sin2_th13 in [0, 1]; dm2_21 > 0;
+ * dm2_32 != 0 (positive: normal ordering) and dm2_32 + dm2_21 != 0, so the
+ * three vacuum levels (0, dm2_21, dm2_32 + dm2_21) are distinct;
+ * delta_cp in radians, finite. */
+typedef struct {
+    double sin2_th12, sin2_th23, sin2_th13;
+    double dm2_32, dm2_21;
+    double delta_cp;
+} osc_params;
+
+/* A Monte Carlo sample in struct-of-arrays layout (Sec. 2.1 keeps the
+ * per-event energies in a device array).  All four arrays are device
+ * pointers with n entries (they may be NULL when n == 0):
+ *   e_true  FP64, true energy in GeV, must be > 0 (not checked per event;
+ *           E <= 0 gives an undefined probability);
+ *   flags   one byte per event: bits 0-1 alpha, bits 2-3 beta (3 is
+ *           invalid), bit 4 antineutrino, bits 5-7 zero.  Invalid flag
+ *           bytes give P = NaN;
+ *   weight  FP64 Monte Carlo weight (only read by osc_fill_pdf);
+ *   e_reco  FP64 reconstructed energy in GeV (only read by osc_fill_pdf).
+ * L_km >= 0, rho_gcc >= 0, 0 <= Ye <= 1 describe the constant-density path. */
+typedef struct {
+    int64_t n;
+    const double* e_true;
+    const uint8_t* flags;
+    const double* weight;
+    const double* e_reco;
+    double L_km, rho_gcc, Ye;
+} osc_sample;
+
+/* Regular binning of the reconstructed energy: nbins bins of width
+ * wb = (hi - lo) / nbins (IEEE FP64).  An event falls into bin
+ * floor((x - lo) / wb) (FP64 subtraction and division), into the underflow
+ * entry when that quotient is negative, and into the overflow entry when it
+ * is >= nbins or NaN.  Histogram layout: nbins bins, underflow, overflow.
+ * 1 <= nbins <= osc_max_nbins(); lo < hi, both finite. */
+typedef struct {
+    int32_t nbins;
+    double lo, hi;
+} osc_binning;
+
+/* Create a context on HIP device `device`.  Returns OSC_ERR_DEVICE when no
+ * GPU is present or the device index is out of range; *out is then NULL. */
+osc_status osc_create(osc_ctx** out, int device);
+
+/* Release a context and its device scratch after waiting for the work it
+ * enqueued.  NULL is accepted. */
+osc_status osc_destroy(osc_ctx* ctx);
+
+/* Check parameter sets without a device (the domain rules of osc_params).
+ * Returns OSC_ERR_INVALID_ARG for the first invalid set. */
+osc_status osc_validate_params(const osc_params* sets, int32_t n_sets);
+
+/* Store n_sets >= 1 parameter sets in the context, replacing earlier ones,
+ * and compute their parameter-only quantities on the host (Sec. 2.1:
+ * mixing matrix, vacuum mass matrix in the flavour basis and its square,
+ * the constants of the characteristic cubic).  The host array is copied;
+ * the caller may free it on return.  Kernels already enqueued keep the
+ * values they were launched with. */
+osc_status osc_set_params(osc_ctx* ctx, const osc_params* sets, int32_t n_sets);
+
+/* Sec. 2.1 (the paper's kernel): write P(alpha -> beta) of every event of
+ * `sample` under parameter set `set` to p_out (device, n FP64 entries,
+ * event order).  weight and e_reco are not read. */
+osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
+                        double* p_out, void* stream);
+
+/* Sec. 1.1.1 event-by-event reweighting: compute P per event, the
+ * contribution c = w * P (rounded separately, never fused), the bin of
+ * e_reco, and the histogram hist_out (device, nbins + 2 FP64 entries,
+ * overwritten).  p_out (device, n entries) may be NULL; when given it
+ * receives P.
+ *
+ * The histogram is bit-reproducible: it is the sum of the c values in a
+ * fixed order that depends only on n and the event order, never on the
+ * launch shape (see osc_reduction_layout): tiles of W*K consecutive events;
+ * lane l of tile t sums events t*W*K + m*W + l for m = 0..K-1 in ascending
+ * m starting from +0.0; per bin, the W lane sums of a tile meet in the
+ * complete binary tree over lane index; the tile results meet in the
+ * complete binary tree over tile index, padded with +0.0 to a power of two. */
+osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
+                        const osc_binning* binning, osc_precision precision,
+                        double* hist_out, double* p_out, void* stream);
+
+/* The reduction of osc_fill_pdf on given per-event values: histogram of
+ * e_reco with contributions c = weight * value (separately rounded), same
+ * binning rule and the same reduction order.  All arrays are device
+ * pointers with n entries; hist_out has nbins + 2 entries. */
+osc_status osc_fill_hist(osc_ctx* ctx, int64_t n, const double* value,
+                         const double* weight, const double* e_reco,
+                         const osc_binning* binning, double* hist_out, void* stream);
+
+/* Device-side timing of the kernels this context launches: while enabled,
+ * every call records hipEvents on its stream around the per-event kernel
+ * and around the histogram merge.  Enabling (on != 0) or disabling drops
+ * earlier records. */
+osc_status osc_profile_enable(osc_ctx* ctx, int on);
+
+/* Wait for the recorded kernels and return the summed durations in
+ * milliseconds and the launch counts of the per-event kernel and of the
+ * merge kernel since the last enable or read; then drop the records.
+ * Any output pointer may be NULL. */
+osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
+                            double* merge_kernel_ms, int64_t* merge_kernel_launches);
+
+/* Constants of the reduction contract: W lanes per tile and K events per
+ * lane.  Either pointer may be NULL. */
+void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events);
+
+/* Largest nbins osc_fill_pdf accepts on this context's device (the
+ * per-lane histograms live in LDS). */
+int32_t osc_max_nbins(const osc_ctx* ctx);
+
+/* Static description of a status code. */
+const char* osc_status_string(osc_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

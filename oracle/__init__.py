@@ -68,6 +68,8 @@ def lib():
         L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, i32, i32, vp, vp]
         L.oracle_fill_pdf.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -86,6 +88,10 @@ def k_matter() -> float:
 
 def num_threads() -> int:
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
 
 
 def pmns(params, anti=False) -> np.ndarray:

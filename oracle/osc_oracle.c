@@ -222,6 +222,15 @@ int oracle_num_threads(void)
 #endif
 }
 
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_prob_batch(const oracle_params* p, double L_km, double rho, double Ye,
                       int64_t n, const double* e_true, const uint8_t* flags,
                       double* p_out)

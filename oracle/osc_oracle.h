@@ -94,8 +94,9 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int32_t nbins, double lo, double hi, int32_t W, int32_t K,
                     double* hist_out, double* p_out);
 
-/* OpenMP thread count the batch functions use. */
+/* OpenMP thread count the batch functions use, and a setter (n > 0). */
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

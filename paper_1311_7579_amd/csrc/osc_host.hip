@@ -1,0 +1,460 @@
+// Host side of libosc: the C ABI of include/osc.h, argument validation,
+// the parameter-only precompute (Sec. 2.1 of arXiv:1311.7579 computes these
+// on the CPU and ships them to the GPU), device scratch, kernel launches.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/osc.h"
+#include "osc_internal.h"
+#include "osc_launch.h"
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// hbar*c = 197.3269804 MeV fm; N_A = 6.02214076e23 / mol (CODATA 2018);
+// G_F / (hbar c)^3 = 1.1663787e-5 GeV^-2.
+constexpr double kHbarcEvM = 197.3269804e-9;
+constexpr double kAvogadro = 6.02214076e23;
+constexpr double kFermiGeV = 1.1663787e-5;
+
+// phase m^2 L / 2E in natural units per (eV^2 km / GeV)
+double phase_constant() { return 1.0e3 / kHbarcEvM / (2.0 * 1.0e9); }
+
+// 2 sqrt(2) G_F N_e E per (g/cm^3 * GeV * Ye), in eV^2
+double matter_constant()
+{
+    const double hbarc_ev_cm = kHbarcEvM * 1.0e2;
+    const double ne_ev3 = kAvogadro * hbarc_ev_cm * hbarc_ev_cm * hbarc_ev_cm;  // per g/cm^3
+    return 2.0 * std::sqrt(2.0) * (kFermiGeV * 1.0e-18) * ne_ev3 * 1.0e9;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+bool params_ok(const osc_params& p)
+{
+    const double s[3] = {p.sin2_th12, p.sin2_th23, p.sin2_th13};
+    for (double v : s)
+        if (!finite(v) || v < 0.0 || v > 1.0) return false;
+    if (!finite(p.dm2_21) || !(p.dm2_21 > 0.0)) return false;
+    if (!finite(p.dm2_32) || p.dm2_32 == 0.0) return false;
+    const double dm31 = p.dm2_32 + p.dm2_21;
+    if (!finite(dm31) || dm31 == 0.0) return false;
+    if (!finite(p.delta_cp)) return false;
+    return true;
+}
+
+// Mixing matrix (PDG form), rows = flavour (e, mu, tau), columns = mass.
+void mixing_matrix(const osc_params& p, cplx U[3][3])
+{
+    const double s12 = std::sqrt(p.sin2_th12), c12 = std::sqrt(1.0 - p.sin2_th12);
+    const double s23 = std::sqrt(p.sin2_th23), c23 = std::sqrt(1.0 - p.sin2_th23);
+    const double s13 = std::sqrt(p.sin2_th13), c13 = std::sqrt(1.0 - p.sin2_th13);
+    const cplx ep = std::polar(1.0, p.delta_cp);     // e^{+i delta}
+    const cplx em = std::conj(ep);
+    U[0][0] = c12 * c13;
+    U[0][1] = s12 * c13;
+    U[0][2] = s13 * em;
+    U[1][0] = -s12 * c23 - c12 * s23 * s13 * ep;
+    U[1][1] = c12 * c23 - s12 * s23 * s13 * ep;
+    U[1][2] = s23 * c13;
+    U[2][0] = s12 * s23 - c12 * c23 * s13 * ep;
+    U[2][1] = -c12 * s23 - s12 * c23 * s13 * ep;
+    U[2][2] = c23 * c13;
+}
+
+// Parameter-only quantities of one set for the kernels.
+osc::SetConsts set_consts(const osc_params& p)
+{
+    cplx U[3][3];
+    mixing_matrix(p, U);
+    const double dm21 = p.dm2_21, dm31 = p.dm2_32 + p.dm2_21;
+    const double lv[3] = {0.0, dm21, dm31};
+
+    cplx H[3][3], H2[3][3];   // U diag(lv) U^+ and U diag(lv^2) U^+
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+            cplx h = 0.0, h2 = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const cplx t = U[b][i] * std::conj(U[a][i]);
+                h += lv[i] * t;
+                h2 += lv[i] * lv[i] * t;
+            }
+            H[b][a] = h;
+            H2[b][a] = h2;
+        }
+
+    osc::SetConsts sc{};
+    sc.T0 = dm21 + dm31;                        // trace of H
+    sc.C0 = dm21 * dm31;                        // sum of principal 2x2 minors of H
+    sc.CA = H[1][1].real() + H[2][2].real();    // d c1 / dA
+    sc.DA = dm21 * dm31 * std::norm(U[0][0]);   // d det / dA = cofactor_ee(H)
+    const double nan = std::nan("");
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a) {
+            osc::Chan& c = sc.ch[(b << 2) | a];
+            if (a == 3 || b == 3) {
+                c = osc::Chan{nan, nan, nan, nan, nan, nan};
+                continue;
+            }
+            cplx g = 0.0;
+            if (b == 0) g += H[0][a];
+            if (a == 0) g += H[b][0];
+            c = osc::Chan{H[b][a].real(), H[b][a].imag(), H2[b][a].real(), H2[b][a].imag(),
+                          g.real(), g.imag()};
+        }
+    return sc;
+}
+
+struct Scratch {
+    void* ptr = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool recorded = false;
+};
+
+constexpr int kScratchSlots = 4;
+
+// hipEvents around the kernels of one call (profiling only)
+struct ProfRec {
+    hipEvent_t start = nullptr, mid = nullptr, end = nullptr;
+};
+
+}  // namespace
+
+struct osc_ctx {
+    int device = 0;
+    size_t max_dyn_lds = 0;
+    int32_t max_nbins = 0;
+    std::vector<osc_params> params;
+    std::vector<osc::SetConsts> consts;
+    Scratch scratch[kScratchSlots];
+    int next_scratch = 0;
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    std::mutex mu;
+};
+
+namespace {
+
+osc_status device_status(hipError_t e) { return e == hipSuccess ? OSC_OK : OSC_ERR_DEVICE; }
+
+void drop_profile(osc_ctx* ctx)
+{
+    for (ProfRec& r : ctx->prof) {
+        for (hipEvent_t e : {r.start, r.mid, r.end})
+            if (e) hipEventDestroy(e);
+    }
+    ctx->prof.clear();
+}
+
+// Starts a profiling record on `stream` when profiling is on.
+ProfRec* prof_begin(osc_ctx* ctx, hipStream_t stream)
+{
+    if (!ctx->profiling) return nullptr;
+    ProfRec r;
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.mid) != hipSuccess ||
+        hipEventCreate(&r.end) != hipSuccess || hipEventRecord(r.start, stream) != hipSuccess) {
+        for (hipEvent_t e : {r.start, r.mid, r.end})
+            if (e) hipEventDestroy(e);
+        return nullptr;
+    }
+    ctx->prof.push_back(r);
+    return &ctx->prof.back();
+}
+
+void prof_mark(hipEvent_t ev, hipStream_t stream)
+{
+    if (ev) hipEventRecord(ev, stream);
+}
+
+// Scratch for one call on `stream`: slots are used round-robin; a reused
+// slot orders the new stream after the last kernel that read it.
+osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scratch** out)
+{
+    Scratch& s = ctx->scratch[ctx->next_scratch];
+    ctx->next_scratch = (ctx->next_scratch + 1) % kScratchSlots;
+    if (s.done == nullptr && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        return OSC_ERR_DEVICE;
+    if (s.cap < bytes) {
+        if (s.ptr) {
+            if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) return OSC_ERR_DEVICE;
+            if (hipFree(s.ptr) != hipSuccess) return OSC_ERR_DEVICE;
+            s.ptr = nullptr;
+            s.cap = 0;
+        }
+        const size_t want = (bytes + (size_t(1) << 20) - 1) & ~((size_t(1) << 20) - 1);
+        if (hipMalloc(&s.ptr, want) != hipSuccess) {
+            s.ptr = nullptr;
+            return OSC_ERR_OUT_OF_MEMORY;
+        }
+        s.cap = want;
+        s.recorded = false;
+    } else if (s.recorded) {
+        if (hipStreamWaitEvent(stream, s.done, 0) != hipSuccess) return OSC_ERR_DEVICE;
+    }
+    *out = &s;
+    return OSC_OK;
+}
+
+osc_status release_scratch(Scratch* s, hipStream_t stream)
+{
+    if (hipEventRecord(s->done, stream) != hipSuccess) return OSC_ERR_DEVICE;
+    s->recorded = true;
+    return OSC_OK;
+}
+
+bool sample_ok(const osc_sample* s, bool needs_hist_inputs)
+{
+    if (!s || s->n < 0 || s->n > osc::kMaxEvents) return false;
+    if (!finite(s->L_km) || s->L_km < 0.0) return false;
+    if (!finite(s->rho_gcc) || s->rho_gcc < 0.0) return false;
+    if (!finite(s->Ye) || s->Ye < 0.0 || s->Ye > 1.0) return false;
+    if (s->n > 0) {
+        if (!s->e_true || !s->flags) return false;
+        if (needs_hist_inputs && (!s->weight || !s->e_reco)) return false;
+    }
+    return true;
+}
+
+bool binning_ok(const osc_ctx* ctx, const osc_binning* b)
+{
+    if (!b || b->nbins < 1 || b->nbins > ctx->max_nbins) return false;
+    if (!finite(b->lo) || !finite(b->hi) || !(b->lo < b->hi)) return false;
+    const double wb = (b->hi - b->lo) / double(b->nbins);
+    return finite(wb) && wb > 0.0;
+}
+
+osc::PathConsts path_consts(const osc_sample* s)
+{
+    return osc::PathConsts{matter_constant() * s->Ye * s->rho_gcc, phase_constant() * s->L_km};
+}
+
+osc::BinConsts bin_consts(const osc_binning* b)
+{
+    return osc::BinConsts{b->lo, (b->hi - b->lo) / double(b->nbins), b->nbins};
+}
+
+// Tile partials + merge for one histogram on `stream`.
+osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, const osc::SetConsts& sc,
+                    const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
+                    const double* e_true, const uint8_t* flags, const double* weight,
+                    const double* e_reco, const double* value, double* p_out,
+                    double* hist_out, hipStream_t stream)
+{
+    const int nbt = bc.nb + 2;
+    const int64_t ntiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
+    const size_t bytes = size_t(nbt) * size_t(ntiles > 0 ? ntiles : 1) * sizeof(double);
+    Scratch* s = nullptr;
+    osc_status st = acquire_scratch(ctx, bytes, stream, &s);
+    if (st != OSC_OK) return st;
+    double* partial = static_cast<double*>(s->ptr);
+    ProfRec* pr = prof_begin(ctx, stream);
+    hipError_t e = osc::launch_tiles(mode, write_p, sc, pc, bc, n, e_true, flags, weight, e_reco,
+                                     value, p_out, partial, stream);
+    if (pr) prof_mark(pr->mid, stream);
+    if (e == hipSuccess) e = osc::launch_merge(partial, n, nbt, hist_out, stream);
+    if (pr) prof_mark(pr->end, stream);
+    st = release_scratch(s, stream);
+    if (e != hipSuccess) return OSC_ERR_DEVICE;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+osc_status osc_create(osc_ctx** out, int device)
+{
+    if (!out) return OSC_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return OSC_ERR_DEVICE;
+    if (device < 0 || device >= count) return OSC_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return OSC_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return OSC_ERR_DEVICE;
+    osc_ctx* ctx = new (std::nothrow) osc_ctx();
+    if (!ctx) return OSC_ERR_OUT_OF_MEMORY;
+    ctx->device = device;
+    // per-lane histograms: (nbins + 2) x 64 lanes x 8 B of dynamic LDS,
+    // next to the 16-entry channel table
+    const size_t static_lds = 16 * sizeof(osc::Chan);
+    size_t lds = prop.sharedMemPerBlock > static_lds ? prop.sharedMemPerBlock - static_lds : 0;
+    if (osc::set_kernel_attributes(lds) != hipSuccess) {
+        // keep to the default 64 KiB per workgroup when the larger limit is refused
+        (void)hipGetLastError();
+        lds = std::min<size_t>(lds, 65536 - static_lds);
+    }
+    const size_t row = size_t(osc::kTileLanes) * sizeof(double);
+    ctx->max_nbins = int32_t(lds / row) - 2;
+    ctx->max_dyn_lds = lds;
+    if (ctx->max_nbins < 1) {
+        delete ctx;
+        return OSC_ERR_DEVICE;
+    }
+    *out = ctx;
+    return OSC_OK;
+}
+
+osc_status osc_destroy(osc_ctx* ctx)
+{
+    if (!ctx) return OSC_OK;
+    osc_status st = OSC_OK;
+    hipSetDevice(ctx->device);
+    drop_profile(ctx);
+    for (Scratch& s : ctx->scratch) {
+        if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
+        if (s.ptr && hipFree(s.ptr) != hipSuccess) st = OSC_ERR_DEVICE;
+        if (s.done && hipEventDestroy(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
+    }
+    delete ctx;
+    return st;
+}
+
+osc_status osc_validate_params(const osc_params* sets, int32_t n_sets)
+{
+    if (!sets || n_sets < 1) return OSC_ERR_INVALID_ARG;
+    for (int32_t k = 0; k < n_sets; ++k)
+        if (!params_ok(sets[k])) return OSC_ERR_INVALID_ARG;
+    return OSC_OK;
+}
+
+osc_status osc_set_params(osc_ctx* ctx, const osc_params* sets, int32_t n_sets)
+{
+    if (!ctx) return OSC_ERR_INVALID_ARG;
+    osc_status st = osc_validate_params(sets, n_sets);
+    if (st != OSC_OK) return st;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    try {
+        ctx->params.assign(sets, sets + n_sets);
+        ctx->consts.resize(size_t(n_sets));
+    } catch (...) {
+        return OSC_ERR_OUT_OF_MEMORY;
+    }
+    for (int32_t k = 0; k < n_sets; ++k) ctx->consts[size_t(k)] = set_consts(sets[k]);
+    return OSC_OK;
+}
+
+osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, double* p_out,
+                        void* stream)
+{
+    if (!ctx || !sample_ok(sample, false)) return OSC_ERR_INVALID_ARG;
+    if (sample->n > 0 && !p_out) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const osc::BinConsts bc{0.0, 1.0, 1};
+    const hipStream_t hs = static_cast<hipStream_t>(stream);
+    ProfRec* pr = prof_begin(ctx, hs);
+    const hipError_t e = osc::launch_tiles(0, true, ctx->consts[size_t(set)], path_consts(sample), bc,
+                                           sample->n, sample->e_true, sample->flags, nullptr,
+                                           nullptr, nullptr, p_out, nullptr, hs);
+    if (pr) {
+        prof_mark(pr->mid, hs);
+        hipEventDestroy(pr->end);
+        pr->end = nullptr;
+    }
+    return device_status(e);
+}
+
+osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
+                        const osc_binning* binning, osc_precision precision, double* hist_out,
+                        double* p_out, void* stream)
+{
+    if (!ctx || !sample_ok(sample, true) || !hist_out) return OSC_ERR_INVALID_ARG;
+    if (!binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
+    if (precision != OSC_FP64) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    return run_hist(ctx, 1, p_out != nullptr, ctx->consts[size_t(set)], path_consts(sample),
+                    bin_consts(binning), sample->n, sample->e_true, sample->flags, sample->weight,
+                    sample->e_reco, nullptr, p_out, hist_out, static_cast<hipStream_t>(stream));
+}
+
+osc_status osc_fill_hist(osc_ctx* ctx, int64_t n, const double* value, const double* weight,
+                         const double* e_reco, const osc_binning* binning, double* hist_out,
+                         void* stream)
+{
+    if (!ctx || n < 0 || n > osc::kMaxEvents || !hist_out) return OSC_ERR_INVALID_ARG;
+    if (n > 0 && (!value || !weight || !e_reco)) return OSC_ERR_INVALID_ARG;
+    if (!binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const osc::SetConsts sc{};
+    const osc::PathConsts pc{0.0, 0.0};
+    return run_hist(ctx, 2, false, sc, pc, bin_consts(binning), n, nullptr, nullptr, weight,
+                    e_reco, value, nullptr, hist_out, static_cast<hipStream_t>(stream));
+}
+
+osc_status osc_profile_enable(osc_ctx* ctx, int on)
+{
+    if (!ctx) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    drop_profile(ctx);
+    ctx->profiling = on != 0;
+    return OSC_OK;
+}
+
+osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
+                            double* merge_kernel_ms, int64_t* merge_kernel_launches)
+{
+    if (!ctx) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    double tile_ms = 0.0, merge_ms = 0.0;
+    int64_t tiles = 0, merges = 0;
+    osc_status st = OSC_OK;
+    for (const ProfRec& r : ctx->prof) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.mid) != hipSuccess ||
+            hipEventElapsedTime(&ms, r.start, r.mid) != hipSuccess) {
+            st = OSC_ERR_DEVICE;
+            break;
+        }
+        tile_ms += ms;
+        ++tiles;
+        if (r.end) {
+            if (hipEventSynchronize(r.end) != hipSuccess ||
+                hipEventElapsedTime(&ms, r.mid, r.end) != hipSuccess) {
+                st = OSC_ERR_DEVICE;
+                break;
+            }
+            merge_ms += ms;
+            ++merges;
+        }
+    }
+    drop_profile(ctx);
+    if (event_kernel_ms) *event_kernel_ms = tile_ms;
+    if (event_kernel_launches) *event_kernel_launches = tiles;
+    if (merge_kernel_ms) *merge_kernel_ms = merge_ms;
+    if (merge_kernel_launches) *merge_kernel_launches = merges;
+    return st;
+}
+
+void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events)
+{
+    if (tile_lanes) *tile_lanes = osc::kTileLanes;
+    if (lane_events) *lane_events = osc::kLaneEvents;
+}
+
+int32_t osc_max_nbins(const osc_ctx* ctx) { return ctx ? ctx->max_nbins : 0; }
+
+const char* osc_status_string(osc_status status)
+{
+    switch (status) {
+        case OSC_OK: return "ok";
+        case OSC_ERR_INVALID_ARG: return "invalid argument";
+        case OSC_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case OSC_ERR_DEVICE: return "no usable device or HIP runtime error";
+        case OSC_ERR_BUDGET: return "over memory budget";
+        case OSC_ERR_NOT_READY: return "not ready";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Internal layout shared by the host side and the kernels of libosc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osc {
+
+// Reduction contract of the binned PDF: a tile is kTileLanes lanes x
+// kLaneEvents events per lane (one wave64 per tile).
+constexpr int kTileLanes = 64;
+constexpr int kLaneEvents = 16;
+constexpr int kTileEvents = kTileLanes * kLaneEvents;
+
+// Largest event count accepted (keeps the tile count within the merge
+// kernel's chunk table).
+constexpr int64_t kMaxEvents = int64_t(1) << 32;
+constexpr int kMergeThreads = 256;
+constexpr int kMergeChunk = 2048;                       // tiles per chunk
+constexpr int kMaxChunks = int((kMaxEvents / kTileEvents) / kMergeChunk);
+
+// One flavour channel (beta <- alpha) of the vacuum mass matrix H0 =
+// U diag(0, dm21, dm31) U^+ in the flavour basis, for neutrinos.
+// With M = H0 + A e_e e_e^T:
+//   M_ba      = m + A [a = b = e]
+//   (M^2)_ba  = m2 + A g + A^2 [a = b = e],  g = [b = e] H0_ea + H0_be [a = e]
+// Antineutrinos use the complex conjugates and the opposite sign of A.
+struct Chan {
+    double m_re, m_im;
+    double m2_re, m2_im;
+    double g_re, g_im;
+};
+
+// Parameter-only quantities of one oscillation parameter set.
+// Characteristic polynomial of M: x^3 - tr x^2 + c1 x - det with
+//   tr = T0 + A,  c1 = C0 + A CA,  det = A DA.
+struct SetConsts {
+    double T0, C0, CA, DA;
+    Chan ch[16];   // index (beta << 2) | alpha; entries with a 3 hold NaN
+};
+
+// Path constants of one sample.
+struct PathConsts {
+    double kA;   // matter term per GeV: A = +-kA * E (eV^2)
+    double kL;   // phase per eV^2 per 1/GeV: phase = kL * lambda / E
+};
+
+struct BinConsts {
+    double lo;
+    double wb;    // (hi - lo) / nbins, computed on the host in FP64
+    int32_t nb;   // regular bins; entries nb and nb + 1 are under/overflow
+};
+
+}  // namespace osc

@@ -1,0 +1,269 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances:
+  * per-event P: 1e-12 absolute (the residual the paper reports between its
+    CPU and GPU double-precision weights, Sec. 2.2);
+  * bin indices and counts: exact;
+  * histograms of given contributions (osc_fill_hist): bit-exact against
+    the oracle's replay of the reduction contract on the same inputs;
+  * histograms of osc_fill_pdf against the oracle's histogram: the P
+    tolerance carried through the weights plus the rounding of both
+    summations, |dh_b| <= 1e-12 * sum_b |w| + 2 d u sum_b |c| with
+    d = K + log2(W) + log2(#tiles padded) additions per contribution and
+    u = 2^-53;
+  * osc_fill_pdf's histogram is bit-identical to osc_fill_hist applied to
+    its own per-event P (the reduction is the same), run to run.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1311_7579_amd import workload
+from helpers import bins_np
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+P_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def osc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_7579_amd import osc as _osc
+    _osc.load()
+    return _osc
+
+
+@pytest.fixture(scope="module")
+def ctx(osc):
+    c = osc.Context(0)
+    c.osc_set_params([workload.TABLE1])
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def gpu_reweight(osc, ctx, s, set_index=0):
+    ds = osc.DeviceSample.from_host(s)
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    ctx.osc_reweight(ds, set_index, p)
+    return host(p)
+
+
+def gpu_fill_pdf(osc, ctx, s, nbins, lo, hi, set_index=0, want_p=True):
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.full((nbins + 2,), -1.0, dtype=torch.float64, device="cuda")
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda") if want_p else None
+    ctx.osc_fill_pdf(ds, set_index, nbins, lo, hi, h, p)
+    return host(h), (host(p) if want_p else None)
+
+
+def hist_tolerance(w, c, bins, nbt, n):
+    W, K = oracle.CONTRACT_W, oracle.CONTRACT_K
+    ntiles = max(1, -(-n // (W * K)))
+    depth = K + int(math.log2(W)) + math.ceil(math.log2(ntiles)) + 1
+    sw = np.bincount(bins, weights=np.abs(w), minlength=nbt)
+    sc = np.bincount(bins, weights=np.abs(c), minlength=nbt)
+    return P_TOL * sw + 2 * depth * 2.0 ** -53 * sc
+
+
+# --------------------------------------------------------------- per event
+def test_c1_plain_fp64_reweight(osc, ctx):
+    """1e5 events, Table 1, 295 km, 2.6 g/cm^3, seed 1."""
+    s = workload.make_sample(100_000, 1)
+    got = gpu_reweight(osc, ctx, s)
+    want = oracle.prob_batch(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags)
+    assert np.abs(got - want).max() <= P_TOL
+
+
+@pytest.mark.parametrize("L,rho", [(295.0, 2.6), (810.0, 2.84), (1300.0, 3.0), (2500.0, 2.4),
+                                   (295.0, 0.0), (0.0, 2.6)])
+def test_all_channels_random_parameters(osc, ctx, L, rho):
+    sets = workload.make_random_physics_sets(6, 17) + workload.make_param_sets(4, 3)
+    ctx.osc_set_params(sets)
+    try:
+        s = workload.make_uniform_energy_sample(40_000, 23, e_max=20.0, e_min=0.05)
+        s.L_km, s.rho_gcc = L, rho
+        for k, p in enumerate(sets):
+            got = gpu_reweight(osc, ctx, s, k)
+            want = oracle.prob_batch(p, L, rho, s.Ye, s.e_true, s.flags)
+            assert np.abs(got - want).max() <= P_TOL, (k, p)
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
+
+
+def test_paper_validation_protocol(osc, ctx):
+    """Sec. 2.2: 1e7 energies uniform on (0, 30] GeV, CPU vs GPU residual
+    of order 1e-12 (every channel, neutrinos and antineutrinos)."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "validation_protocol.json")))
+    s = workload.make_uniform_energy_sample(g["n_events"], 31, e_max=g["e_max_GeV"])
+    got = gpu_reweight(osc, ctx, s)
+    want = oracle.prob_batch(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags)
+    assert np.abs(got - want).max() <= g["residual_abs"]
+
+
+def test_invalid_flags_give_nan(osc, ctx):
+    s = workload.make_sample(300, 2)
+    s.flags[[0, 5, 77, 299]] = np.array([3, 3 << 2, 1 << 5, 0xFF], dtype=np.uint8)
+    got = gpu_reweight(osc, ctx, s)
+    assert np.isnan(got[[0, 5, 77, 299]]).all()
+    ok = np.ones(300, bool)
+    ok[[0, 5, 77, 299]] = False
+    assert np.isfinite(got[ok]).all()
+
+
+def test_probabilities_bounded_and_unitary(osc, ctx):
+    # sum over final flavours is 1 for every initial flavour
+    n = 30_000
+    rng = np.random.default_rng(4)
+    E = 10 ** rng.uniform(-1, 1.3, n)
+    for anti in (0, 1):
+        tot = np.zeros(n)
+        for a in range(3):
+            tot[:] = 0
+            for b in range(3):
+                s = workload.Sample(e_true=E, flags=workload.make_flags(np.full(n, a), np.full(n, b),
+                                                                        np.full(n, anti, bool)),
+                                    weight=np.ones(n), e_reco=E, L_km=1300.0, rho_gcc=2.8)
+                p = gpu_reweight(osc, ctx, s)
+                assert p.min() >= -1e-15 and p.max() <= 1 + 1e-12
+                tot += p
+            assert np.abs(tot - 1).max() < 1e-12
+
+
+# --------------------------------------------------------------- histograms
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1023, 1024, 1025, 123_457, 1_000_003])
+def test_fill_hist_bit_exact_vs_contract(osc, ctx, n):
+    rng = np.random.default_rng(n)
+    v = rng.uniform(0.0, 1.0, n)
+    w = rng.uniform(0.5, 1.5, n)
+    x = rng.uniform(-0.3, 3.3, n)
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(v), dev(w), dev(x), 50, 0.0, 3.0, h)
+    bins = oracle.bin_indices(x, 0.0, 3.0, 50) if n <= 200_000 else bins_np(x, 0.0, 3.0, 50)
+    want = oracle.hist_contract(w * v, bins, 52)
+    np.testing.assert_array_equal(host(h), want)
+
+
+@pytest.mark.parametrize("nbins,lo,hi", [(1, 0.0, 3.0), (7, 0.5, 2.0), (200, 0.0, 10.0)])
+def test_fill_hist_counts_exact(osc, ctx, nbins, lo, hi):
+    n = 200_003
+    x = np.random.default_rng(nbins).uniform(lo - 0.5, hi + 0.5, n)
+    x[:50] = lo
+    x[50:100] = hi
+    one = np.ones(n)
+    h = torch.empty(nbins + 2, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(one), dev(one), dev(x), nbins, lo, hi, h)
+    bins = oracle.bin_indices(x, lo, hi, nbins)
+    np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=nbins + 2).astype(float))
+
+
+def test_fill_hist_max_nbins(osc, ctx):
+    nb = ctx.max_nbins
+    assert nb >= 200
+    n = 100_000
+    rng = np.random.default_rng(5)
+    v, w, x = rng.uniform(0, 1, n), rng.uniform(0.5, 1.5, n), rng.uniform(-1, 11, n)
+    h = torch.empty(nb + 2, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(v), dev(w), dev(x), nb, 0.0, 10.0, h)
+    want = oracle.hist_contract(w * v, oracle.bin_indices(x, 0.0, 10.0, nb), nb + 2)
+    np.testing.assert_array_equal(host(h), want)
+    with pytest.raises(osc.OscError):
+        ctx.osc_fill_hist(dev(v), dev(w), dev(x), nb + 1, 0.0, 10.0,
+                          torch.empty(nb + 3, dtype=torch.float64, device="cuda"))
+
+
+def test_c2_fill_pdf_full_size(osc, ctx):
+    """1e7 events, 50 bins on [0, 3] GeV: per-event P within 1e-12 of the
+    oracle, histogram within the carried tolerance, and bit-identical to
+    the contract applied to the GPU's own P."""
+    s = workload.make_sample(10_000_000, 1)
+    h, p = gpu_fill_pdf(osc, ctx, s, 50, 0.0, 3.0)
+    hist_o, p_o = oracle.fill_pdf(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                  s.weight, s.e_reco, 50, 0.0, 3.0)
+    assert np.abs(p - p_o).max() <= P_TOL
+    bins = bins_np(s.e_reco, 0.0, 3.0, 50)
+    tol = hist_tolerance(s.weight, s.weight * p_o, bins, 52, s.n)
+    assert (np.abs(h - hist_o) <= tol).all(), np.abs(h - hist_o).max()
+    # bit-exact reduction of the GPU's own contributions (same fixed order)
+    hh = torch.empty(52, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(p), dev(s.weight), dev(s.e_reco), 50, 0.0, 3.0, hh)
+    np.testing.assert_array_equal(host(hh), h)
+
+
+def test_fill_pdf_deterministic_and_p_optional(osc, ctx):
+    s = workload.make_sample(2_000_001, 7)
+    ds = osc.DeviceSample.from_host(s)
+    outs = []
+    for k in range(3):
+        h = torch.empty(52, dtype=torch.float64, device="cuda")
+        if k == 2:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, None)
+            st.synchronize()
+        else:
+            p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+            ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, p if k == 0 else None)
+        outs.append(host(h))
+    np.testing.assert_array_equal(outs[0], outs[1])
+    np.testing.assert_array_equal(outs[0], outs[2])
+
+
+def test_fill_pdf_small_and_ragged_against_contract(osc, ctx):
+    for n in (1, 65, 1025, 50_001):
+        s = workload.make_sample(n, 100 + n)
+        h, p = gpu_fill_pdf(osc, ctx, s, 50, 0.0, 3.0)
+        hist_o, p_o = oracle.fill_pdf(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true,
+                                      s.flags, s.weight, s.e_reco, 50, 0.0, 3.0)
+        assert np.abs(p - p_o).max() <= P_TOL
+        bins = oracle.bin_indices(s.e_reco, 0.0, 3.0, 50)
+        tol = hist_tolerance(s.weight, s.weight * p_o, bins, 52, n)
+        assert (np.abs(h - hist_o) <= tol).all()
+        np.testing.assert_array_equal(h, oracle.hist_contract(s.weight * p, bins, 52))
+
+
+def test_empty_sample(osc, ctx):
+    s = workload.make_sample(0, 1)
+    h, p = gpu_fill_pdf(osc, ctx, s, 50, 0.0, 3.0)
+    assert (h == 0.0).all() and p.size == 0
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    hh = torch.full((52,), 7.0, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(e, e, e, 50, 0.0, 3.0, hh)
+    assert (host(hh) == 0.0).all()
+
+
+def test_invalid_arguments_raise(osc, ctx):
+    s = osc.DeviceSample.from_host(workload.make_sample(100, 1))
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    p = torch.empty(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(osc.OscError):
+        ctx.osc_fill_pdf(s, 1, 50, 0.0, 3.0, h)          # no such set
+    with pytest.raises(osc.OscError):
+        ctx.osc_fill_pdf(s, 0, 50, 3.0, 3.0, h)          # empty range
+    with pytest.raises(osc.OscError):
+        ctx.osc_fill_pdf(s, 0, 0, 0.0, 3.0, h)           # no bins
+    with pytest.raises(osc.OscError):
+        ctx.osc_reweight(s, -1, p)
+    bad = osc.DeviceSample(s.e_true, s.flags, s.weight, s.e_reco, L_km=-1.0)
+    with pytest.raises(osc.OscError):
+        ctx.osc_reweight(bad, 0, p)
+    with pytest.raises(osc.OscError):
+        ctx.osc_set_params([dict(workload.TABLE1, dm2_21=0.0)])
+    # the context still works after rejected calls
+    ctx.osc_reweight(s, 0, p)
+    assert np.isfinite(host(p)).all()

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
+from helpers import bins_np
 from paper_1311_7579_amd import workload
 
 
@@ -138,3 +139,11 @@ def test_fill_pdf_composes_prob_bins_and_contract():
     # with P = 1 everywhere the PDF is the plain weighted histogram
     assert hist.sum() == pytest.approx(math.fsum(c), rel=1e-13)
     assert hist[51] > 0.2 * hist.sum()   # E_reco > 3 GeV tail of the log-uniform spectrum
+
+
+def test_vectorised_bin_rule_matches_oracle():
+    x = np.random.default_rng(0).uniform(-0.5, 3.5, 20_000)
+    x[:3] = [0.0, 3.0, np.nan]
+    np.testing.assert_array_equal(bins_np(x, 0.0, 3.0, 50), oracle.bin_indices(x, 0.0, 3.0, 50))
+    x2 = np.random.default_rng(1).uniform(0.0, 10.0, 5_000)
+    np.testing.assert_array_equal(bins_np(x2, 0.5, 9.5, 37), oracle.bin_indices(x2, 0.5, 9.5, 37))
