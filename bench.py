@@ -39,12 +39,31 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--latency-calls", type=int, default=1000)
-    ap.add_argument("--cpu-events", type=int, default=2_000_000,
+    ap.add_argument("--cpu-events", type=int, default=10_000_000,
                     help="events of the oracle's timed slice (all host threads)")
-    ap.add_argument("--cpu-events-1t", type=int, default=200_000,
+    ap.add_argument("--cpu-events-1t", type=int, default=1_000_000,
                     help="events of the oracle's single-thread slice")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision-form measurement (64 parameter sets, both tiers)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run torch device-to-device copies of MIB MiB (HBM counter "
+                         "calibration under rocprofv3) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib, reps=5):
+    """Plain device copies of a known size: the HBM byte counters of these
+    dispatches calibrate the counters of the kernels above."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_MiB": mib, "bytes_read_per_copy": n * 8,
+                      "bytes_written_per_copy": n * 8, "reps": reps}), flush=True)
 
 
 def cpu_baseline(sample, n_all, n_one):
@@ -73,8 +92,48 @@ def cpu_baseline(sample, n_all, n_one):
     }
 
 
+def precision_form(osc, ctx, ds, n_sets=64, set_seed=3):
+    """The 1e7 events under 64 parameter sets, once per tier: throughput of
+    each tier and the largest |P_mixed - P_fp64| over all events and sets."""
+    import torch
+    from paper_1311_7579_amd import workload
+    sets = workload.make_param_sets(n_sets, set_seed)
+    ctx.osc_set_params(sets)
+    n = ds.n
+    h = torch.empty(NBINS + 2, dtype=torch.float64, device="cuda")
+    p64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    pmx = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, prec, buf in (("fp64", osc.OSC_FP64, p64), ("fp32_mixed", osc.OSC_FP32_MIXED, pmx)):
+        for k in range(2):   # warm-up
+            ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, buf, precision=prec)
+        torch.cuda.synchronize()
+        ctx.osc_profile_enable(True)
+        t0 = time.perf_counter()
+        for k in range(n_sets):
+            ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, buf, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
+        ctx.osc_profile_enable(False)
+        out[name] = {"evals_per_s": n * n_sets / dt, "kernel_ms": ev_ms / max(ev_n, 1),
+                     "merge_ms": merge_ms / max(merge_n, 1)}
+    worst = 0.0
+    for k in range(n_sets):
+        ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, p64, precision=osc.OSC_FP64)
+        ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, pmx, precision=osc.OSC_FP32_MIXED)
+        worst = max(worst, float((pmx - p64).abs().max()))
+    out["max_abs_dP_mixed_vs_fp64"] = worst
+    out["config"] = f"{n} events x {n_sets} parameter sets (seed {set_seed}), P written"
+    ctx.osc_set_params([workload.TABLE1])
+    return out
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the path shards by events or parameter sets, see the design notes)", flush=True)
@@ -118,6 +177,7 @@ def main():
     ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
     ctx.osc_profile_enable(False)
     kernel_ms = ev_ms / max(ev_n, 1)
+    waves_per_cu = ctx.osc_occupancy(NBINS, True)
     merge_avg_ms = merge_ms / max(merge_n, 1)
 
     # end-to-end latency of single calls: launch -> histogram on the host
@@ -128,7 +188,7 @@ def main():
         step()
         host_hist.copy_(hist, non_blocking=False)
         lat.append(time.perf_counter() - a)
-    lat = np.array(lat) * 1e3
+    lat = np.array(lat if lat else [float("nan")]) * 1e3
 
     achieved_gbs = BYTES_PER_EVENT * N_EVENTS / (kernel_ms * 1e-3) / 1e9
     roofline = {
@@ -137,6 +197,7 @@ def main():
         "kernel": "tile_kernel<kPdf, write P>", "kernel_ms": kernel_ms,
         "merge_kernel_ms": merge_avg_ms,
         "algorithmic_bytes_per_event": BYTES_PER_EVENT,
+        "resident_waves_per_cu": waves_per_cu,
     }
 
     result = {
@@ -152,6 +213,8 @@ def main():
                        "calls": args.latency_calls},
         "roofline": roofline,
     }
+    if not args.no_forms:
+        result["precision_form"] = precision_form(osc, ctx, ds)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(s, args.cpu_events, args.cpu_events_1t)
         result["speedup_vs_cpu_all_cores"] = value / result["cpu_baseline"]["value"]

@@ -163,6 +163,11 @@ void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events);
  * per-lane histograms live in LDS). */
 int32_t osc_max_nbins(const osc_ctx* ctx);
 
+/* Resident waves per compute unit of the per-event kernel (one wave per
+ * tile): for osc_fill_pdf with `nbins` bins when with_hist != 0, for
+ * osc_reweight otherwise.  *waves_per_cu receives the count. */
+osc_status osc_occupancy(const osc_ctx* ctx, int32_t nbins, int with_hist, int32_t* waves_per_cu);
+
 /* Static description of a status code. */
 const char* osc_status_string(osc_status status);
 

@@ -18,8 +18,11 @@ ARCH = os.environ.get("OSC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=fast", "-Wall",
+    "-ffp-contract=fast-honor-pragmas", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # interleave independent events within a wave (occupancy is bounded by
+    # the LDS histograms, not by registers)
+    "-mllvm", "-amdgpu-sched-strategy=max-ilp",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -192,6 +192,9 @@ osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scrat
             s.ptr = nullptr;
             return OSC_ERR_OUT_OF_MEMORY;
         }
+        // the merge kernel's arrival counter starts at zero (the kernel
+        // resets it after every use)
+        if (hipMemset(s.ptr, 0, osc::kMergeCounterBytes) != hipSuccess) return OSC_ERR_DEVICE;
         s.cap = want;
         s.recorded = false;
     } else if (s.recorded) {
@@ -236,28 +239,26 @@ osc::PathConsts path_consts(const osc_sample* s)
 
 osc::BinConsts bin_consts(const osc_binning* b)
 {
-    return osc::BinConsts{b->lo, (b->hi - b->lo) / double(b->nbins), b->nbins};
+    const double wb = (b->hi - b->lo) / double(b->nbins);
+    return osc::BinConsts{b->lo, wb, 1.0 / wb, b->nbins};
 }
 
 // Tile partials + merge for one histogram on `stream`.
-osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, const osc::SetConsts& sc,
+osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
                     const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
                     const double* e_true, const uint8_t* flags, const double* weight,
                     const double* e_reco, const double* value, double* p_out,
                     double* hist_out, hipStream_t stream)
 {
     const int nbt = bc.nb + 2;
-    const int64_t ntiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
-    const size_t bytes = size_t(nbt) * size_t(ntiles > 0 ? ntiles : 1) * sizeof(double);
     Scratch* s = nullptr;
-    osc_status st = acquire_scratch(ctx, bytes, stream, &s);
+    osc_status st = acquire_scratch(ctx, osc::merge_scratch_bytes(n, nbt), stream, &s);
     if (st != OSC_OK) return st;
-    double* partial = static_cast<double*>(s->ptr);
     ProfRec* pr = prof_begin(ctx, stream);
-    hipError_t e = osc::launch_tiles(mode, write_p, sc, pc, bc, n, e_true, flags, weight, e_reco,
-                                     value, p_out, partial, stream);
+    hipError_t e = osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags, weight,
+                                     e_reco, value, p_out, osc::scratch_partials(s->ptr), stream);
     if (pr) prof_mark(pr->mid, stream);
-    if (e == hipSuccess) e = osc::launch_merge(partial, n, nbt, hist_out, stream);
+    if (e == hipSuccess) e = osc::launch_merge(s->ptr, n, nbt, hist_out, stream);
     if (pr) prof_mark(pr->end, stream);
     st = release_scratch(s, stream);
     if (e != hipSuccess) return OSC_ERR_DEVICE;
@@ -282,8 +283,8 @@ osc_status osc_create(osc_ctx** out, int device)
     if (!ctx) return OSC_ERR_OUT_OF_MEMORY;
     ctx->device = device;
     // per-lane histograms: (nbins + 2) x 64 lanes x 8 B of dynamic LDS,
-    // next to the 16-entry channel table
-    const size_t static_lds = 16 * sizeof(osc::Chan);
+    // next to the 9-entry channel table
+    const size_t static_lds = 9 * sizeof(osc::Chan);
     size_t lds = prop.sharedMemPerBlock > static_lds ? prop.sharedMemPerBlock - static_lds : 0;
     if (osc::set_kernel_attributes(lds) != hipSuccess) {
         // keep to the default 64 KiB per workgroup when the larger limit is refused
@@ -348,10 +349,11 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, dou
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
-    const osc::BinConsts bc{0.0, 1.0, 1};
+    const osc::BinConsts bc{0.0, 1.0, 1.0, 1};
     const hipStream_t hs = static_cast<hipStream_t>(stream);
     ProfRec* pr = prof_begin(ctx, hs);
-    const hipError_t e = osc::launch_tiles(0, true, ctx->consts[size_t(set)], path_consts(sample), bc,
+    const hipError_t e = osc::launch_tiles(0, true, false, ctx->consts[size_t(set)],
+                                           path_consts(sample), bc,
                                            sample->n, sample->e_true, sample->flags, nullptr,
                                            nullptr, nullptr, p_out, nullptr, hs);
     if (pr) {
@@ -368,11 +370,12 @@ osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
 {
     if (!ctx || !sample_ok(sample, true) || !hist_out) return OSC_ERR_INVALID_ARG;
     if (!binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
-    if (precision != OSC_FP64) return OSC_ERR_INVALID_ARG;
+    if (precision != OSC_FP64 && precision != OSC_FP32_MIXED) return OSC_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
-    return run_hist(ctx, 1, p_out != nullptr, ctx->consts[size_t(set)], path_consts(sample),
+    return run_hist(ctx, 1, p_out != nullptr, precision == OSC_FP32_MIXED, ctx->consts[size_t(set)],
+                    path_consts(sample),
                     bin_consts(binning), sample->n, sample->e_true, sample->flags, sample->weight,
                     sample->e_reco, nullptr, p_out, hist_out, static_cast<hipStream_t>(stream));
 }
@@ -388,7 +391,7 @@ osc_status osc_fill_hist(osc_ctx* ctx, int64_t n, const double* value, const dou
     if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
     const osc::SetConsts sc{};
     const osc::PathConsts pc{0.0, 0.0};
-    return run_hist(ctx, 2, false, sc, pc, bin_consts(binning), n, nullptr, nullptr, weight,
+    return run_hist(ctx, 2, false, false, sc, pc, bin_consts(binning), n, nullptr, nullptr, weight,
                     e_reco, value, nullptr, hist_out, static_cast<hipStream_t>(stream));
 }
 
@@ -443,6 +446,17 @@ void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events)
 }
 
 int32_t osc_max_nbins(const osc_ctx* ctx) { return ctx ? ctx->max_nbins : 0; }
+
+osc_status osc_occupancy(const osc_ctx* ctx, int32_t nbins, int with_hist, int32_t* waves_per_cu)
+{
+    if (!ctx || !waves_per_cu) return OSC_ERR_INVALID_ARG;
+    if (with_hist && (nbins < 1 || nbins > ctx->max_nbins)) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    int blocks = 0;
+    if (osc::occupancy(with_hist ? 1 : 0, nbins, &blocks) != hipSuccess) return OSC_ERR_DEVICE;
+    *waves_per_cu = blocks;
+    return OSC_OK;
+}
 
 const char* osc_status_string(osc_status status)
 {

@@ -12,12 +12,23 @@ constexpr int kTileLanes = 64;
 constexpr int kLaneEvents = 16;
 constexpr int kTileEvents = kTileLanes * kLaneEvents;
 
-// Largest event count accepted (keeps the tile count within the merge
-// kernel's chunk table).
+// Largest event count accepted.
 constexpr int64_t kMaxEvents = int64_t(1) << 32;
+// Histogram merge: 256-thread blocks, each reducing an aligned chunk of
+// kMergeChunkTiles tile results per bin.  The scratch buffer starts with the
+// merge's arrival counter (kMergeCounterBytes, zeroed when the buffer is
+// allocated, reset by the kernel after every use), then holds the tile
+// results (bin-major within each chunk), then the chunk results.
 constexpr int kMergeThreads = 256;
-constexpr int kMergeChunk = 2048;                       // tiles per chunk
-constexpr int kMaxChunks = int((kMaxEvents / kTileEvents) / kMergeChunk);
+constexpr int kMergeChunkTiles = 128;
+constexpr size_t kMergeCounterBytes = 256;
+
+// Position of the result of (tile, bin) among the tile results.
+__host__ __device__ inline int64_t partial_index(int64_t tile, int bin, int nbt)
+{
+    return (tile / kMergeChunkTiles) * int64_t(nbt) * kMergeChunkTiles +
+           int64_t(bin) * kMergeChunkTiles + (tile % kMergeChunkTiles);
+}
 
 // One flavour channel (beta <- alpha) of the vacuum mass matrix H0 =
 // U diag(0, dm21, dm31) U^+ in the flavour basis, for neutrinos.
@@ -47,8 +58,9 @@ struct PathConsts {
 
 struct BinConsts {
     double lo;
-    double wb;    // (hi - lo) / nbins, computed on the host in FP64
-    int32_t nb;   // regular bins; entries nb and nb + 1 are under/overflow
+    double wb;      // (hi - lo) / nbins, computed on the host in FP64
+    double inv_wb;  // 1 / wb rounded to FP64 (fast path of the bin index)
+    int32_t nb;     // regular bins; entries nb and nb + 1 are under/overflow
 };
 
 }  // namespace osc

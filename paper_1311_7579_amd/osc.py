@@ -87,6 +87,8 @@ def load():
     L.osc_profile_read.restype = st
     L.osc_reduction_layout.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.osc_reduction_layout.restype = None
+    L.osc_occupancy.argtypes = [vp, i32, ctypes.c_int, ctypes.POINTER(i32)]
+    L.osc_occupancy.restype = st
     L.osc_max_nbins.argtypes = [vp]
     L.osc_max_nbins.restype = i32
     L.osc_status_string.argtypes = [ctypes.c_int]
@@ -203,6 +205,12 @@ class Context:
     @property
     def max_nbins(self) -> int:
         return load().osc_max_nbins(self.handle)
+
+    def osc_occupancy(self, nbins=50, with_hist=True) -> int:
+        w = ctypes.c_int32()
+        _check(load().osc_occupancy(self.handle, int(nbins), int(bool(with_hist)), ctypes.byref(w)),
+               "osc_occupancy")
+        return w.value
 
     def osc_set_params(self, sets):
         arr = params_array(sets)

@@ -32,7 +32,8 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for want in ("osc_create", "osc_destroy", "osc_set_params", "osc_reweight", "osc_fill_pdf",
                  "osc_fill_hist", "osc_validate_params", "osc_reduction_layout",
-                 "osc_max_nbins", "osc_status_string"):
+                 "osc_max_nbins", "osc_status_string", "osc_occupancy", "osc_profile_enable",
+                 "osc_profile_read"):
         assert want in names
 
 

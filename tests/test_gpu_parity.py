@@ -159,6 +159,20 @@ def test_fill_hist_bit_exact_vs_contract(osc, ctx, n):
     np.testing.assert_array_equal(host(h), want)
 
 
+def test_fill_hist_multilevel_merge_bit_exact(osc, ctx):
+    """2e7 events = 19532 tiles = 153 merge chunks: the merge needs a second
+    level above the chunks; the bits must still follow the contract."""
+    n = 20_000_000
+    rng = np.random.default_rng(77)
+    v = rng.uniform(0.0, 1.0, n)
+    w = rng.uniform(0.5, 1.5, n)
+    x = rng.uniform(-0.2, 3.2, n)
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(v), dev(w), dev(x), 50, 0.0, 3.0, h)
+    want = oracle.hist_contract(w * v, bins_np(x, 0.0, 3.0, 50), 52)
+    np.testing.assert_array_equal(host(h), want)
+
+
 @pytest.mark.parametrize("nbins,lo,hi", [(1, 0.0, 3.0), (7, 0.5, 2.0), (200, 0.0, 10.0)])
 def test_fill_hist_counts_exact(osc, ctx, nbins, lo, hi):
     n = 200_003
@@ -170,6 +184,32 @@ def test_fill_hist_counts_exact(osc, ctx, nbins, lo, hi):
     ctx.osc_fill_hist(dev(one), dev(one), dev(x), nbins, lo, hi, h)
     bins = oracle.bin_indices(x, lo, hi, nbins)
     np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=nbins + 2).astype(float))
+
+
+@pytest.mark.parametrize("nbins,lo,hi", [(50, 0.0, 3.0), (37, 0.5, 9.5), (316, -1.0, 0.7)])
+def test_fill_hist_bin_edges_exact(osc, ctx, nbins, lo, hi):
+    """Values on every bin edge and on the three neighbouring doubles either
+    side: bin indices (hence counts) must equal the FP64 quotient rule."""
+    nbins = min(nbins, ctx.max_nbins)
+    wb = (hi - lo) / nbins
+    x = []
+    for k in range(-2, nbins + 3):
+        e = lo + k * wb
+        x.append(e)
+        up = dn = e
+        for _ in range(3):
+            up, dn = np.nextafter(up, np.inf), np.nextafter(dn, -np.inf)
+            x += [up, dn]
+    x = np.array(x + [np.nan, np.inf, -np.inf, -0.0, 1e300, -1e300])
+    one = np.ones(x.size)
+    h = torch.empty(nbins + 2, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(one), dev(one), dev(x), nbins, lo, hi, h)
+    bins = oracle.bin_indices(x, lo, hi, nbins)
+    np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=nbins + 2).astype(float))
+    # weights of distinct powers of two identify which event went where
+    w = 2.0 ** -np.arange(x.size % 50 + 1)[np.arange(x.size) % (x.size % 50 + 1)]
+    ctx.osc_fill_hist(dev(one), dev(w), dev(x), nbins, lo, hi, h)
+    np.testing.assert_array_equal(host(h), oracle.hist_contract(w, bins, nbins + 2))
 
 
 def test_fill_hist_max_nbins(osc, ctx):
@@ -267,3 +307,71 @@ def test_invalid_arguments_raise(osc, ctx):
     # the context still works after rejected calls
     ctx.osc_reweight(s, 0, p)
     assert np.isfinite(host(p)).all()
+
+
+# --------------------------------------------------------------- FP32-mixed tier
+# FP64 eigenvalues and phase differences, FP32 sine/cosine and amplitude
+# assembly.  The tolerance comes from the FP32 rounding of the amplitude
+# inputs: N_k carries ~|u m| 2^-24 ~ 4e-13 eV^4 of rounding, divided by
+# D_k >= ~1.7e-7 eV^4 near the solar resonance, i.e. ~2e-6 per projector
+# element; the hardware sine/cosine add ~1e-6.  The bound below doubles the
+# sum over the three projector terms.
+MIXED_TOL = 2e-5
+
+
+def test_mixed_tier_c3_parameter_sets(osc, ctx):
+    """1e7 events x 64 parameter sets (C3 draw): mixed-tier P within
+    MIXED_TOL of the FP64 tier on every event and of the oracle on a 1e5
+    subsample; histograms within the carried bound; the reduction of the
+    mixed tier's own P is bit-exact."""
+    sets = workload.make_param_sets(64, 3)
+    s = workload.make_sample(10_000_000, 1)
+    ds = osc.DeviceSample.from_host(s)
+    sub = slice(0, 100_000)
+    ctx.osc_set_params(sets)
+    try:
+        h64 = torch.empty(52, dtype=torch.float64, device="cuda")
+        hmx = torch.empty(52, dtype=torch.float64, device="cuda")
+        p64 = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        pmx = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        worst_gpu, worst_oracle = 0.0, 0.0
+        for k, p in enumerate(sets):
+            ctx.osc_fill_pdf(ds, k, 50, 0.0, 3.0, h64, p64, precision=osc.OSC_FP64)
+            ctx.osc_fill_pdf(ds, k, 50, 0.0, 3.0, hmx, pmx, precision=osc.OSC_FP32_MIXED)
+            d = float((pmx - p64).abs().max())
+            worst_gpu = max(worst_gpu, d)
+            po = oracle.prob_batch(p, s.L_km, s.rho_gcc, s.Ye, s.e_true[sub], s.flags[sub])
+            worst_oracle = max(worst_oracle, float(np.abs(host(pmx[sub]) - po).max()))
+            assert np.abs(host(p64[sub]) - po).max() <= P_TOL
+            hm = host(hmx)
+            bins = bins_np(s.e_reco, 0.0, 3.0, 50)
+            sw = np.bincount(bins, weights=s.weight, minlength=52)
+            assert (np.abs(hm - host(h64)) <= MIXED_TOL * sw + 1e-9).all()
+            if k % 16 == 0:
+                hh = torch.empty(52, dtype=torch.float64, device="cuda")
+                ctx.osc_fill_hist(pmx, ds.weight, ds.e_reco, 50, 0.0, 3.0, hh)
+                np.testing.assert_array_equal(host(hh), hm)
+        print(f"mixed tier: max |P_mixed - P_fp64| = {worst_gpu:.3g}, "
+              f"max |P_mixed - P_oracle| (1e5 x 64) = {worst_oracle:.3g}")
+        assert worst_gpu <= MIXED_TOL
+        assert worst_oracle <= MIXED_TOL
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
+
+
+def test_mixed_tier_all_channels(osc, ctx):
+    sets = workload.make_random_physics_sets(4, 29) + [workload.TABLE1]
+    ctx.osc_set_params(sets)
+    try:
+        s = workload.make_uniform_energy_sample(200_000, 37, e_max=20.0, e_min=0.05)
+        for L, rho in ((295.0, 2.6), (2500.0, 2.8), (810.0, 0.0)):
+            s.L_km, s.rho_gcc = L, rho
+            ds = osc.DeviceSample.from_host(s)
+            for k, p in enumerate(sets):
+                h = torch.empty(52, dtype=torch.float64, device="cuda")
+                pm = torch.empty(s.n, dtype=torch.float64, device="cuda")
+                ctx.osc_fill_pdf(ds, k, 50, 0.0, 3.0, h, pm, precision=osc.OSC_FP32_MIXED)
+                po = oracle.prob_batch(p, L, rho, s.Ye, s.e_true, s.flags)
+                assert np.abs(host(pm) - po).max() <= MIXED_TOL, (L, rho, k)
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
