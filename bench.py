@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form measurement (64 parameter sets, both tiers)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving-form measurement (Poisson proposal streams)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-form measurement (256 sets x 4 uneven samples)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run torch device-to-device copies of MIB MiB (HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -126,6 +131,76 @@ def precision_form(osc, ctx, ds, n_sets=64, set_seed=3):
     out["max_abs_dP_mixed_vs_fp64"] = worst
     out["config"] = f"{n} events x {n_sets} parameter sets (seed {set_seed}), P written"
     ctx.osc_set_params([workload.TABLE1])
+    return out
+
+
+def batched_form(osc, ctx, reps=5):
+    """256 parameter sets x 4 samples of 1e5, 5e5, 2e6 and 5e6 events (295,
+    810, 1300, 2500 km; densities U(2.4, 3.0)), mixed tier, one batched
+    launch per step after autotuning."""
+    import torch
+    from paper_1311_7579_amd import workload
+    samples = workload.make_batched_samples()
+    ds = [osc.DeviceSample.from_host(s) for s in samples]
+    sets = workload.make_param_sets(256, 4)
+    evals = sum(s.n for s in samples) * len(sets)
+    out = {"config": "256 sets x 4 samples (1e5, 5e5, 2e6, 5e6 events), FP32-mixed tier, "
+                     "50 bins, hipGraph replay", "evals_per_launch": evals}
+    batch = osc.Batch(ctx, ds, NBINS, LO, HI, precision=osc.OSC_FP32_MIXED, max_sets=256)
+    try:
+        t0 = time.perf_counter()
+        out["tune_best_ms"] = batch.tune(sets)
+        out["tune_s"] = time.perf_counter() - t0
+        out["tuned_config"] = batch.config.as_dict()
+        hist = torch.empty((256, 4, NBINS + 2), dtype=torch.float64, device="cuda")
+        batch.run(sets, hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batch.run(sets, hist)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["ms_per_launch"] = dt * 1e3
+        out["evals_per_s"] = evals / dt
+    finally:
+        batch.close()
+    return out
+
+
+SERVE_BUDGET = 24 << 20    # device scratch shared by requests in flight
+
+
+def serving_form(osc, ctx, n_requests):
+    """8 resident samples of 1e4 .. 2e7 events, MCMC-style proposals (1 %
+    steps, half in each precision tier) on 8 slots with a 24 MiB scratch
+    budget: saturation throughput from a burst, then Poisson streams at
+    0.5, 0.8 and 0.95 of it with p50/p99 latency."""
+    from paper_1311_7579_amd import serving, workload
+    samples = workload.make_serving_samples()
+    ds = [osc.DeviceSample.from_host(s) for s in samples]
+    ev = [s.n for s in samples]
+    out = {"config": "8 samples (1e4..2e7 events, 3.02e7 total), 8 slots, 24 MiB scratch "
+                     "budget, 50 % FP64 / 50 % FP32-mixed, 1 % MCMC steps",
+           "requests_per_run": n_requests}
+    server = osc.Server(ctx, ds, NBINS, LO, HI, slots=8, scratch_budget_bytes=SERVE_BUDGET)
+    try:
+        warm = workload.make_proposal_stream(64, 500, len(ds))
+        serving.run_stream(server, warm, [0.0] * len(warm), ev)
+        reqs = workload.make_proposal_stream(n_requests, 501, len(ds))
+        _, sat = serving.run_stream(server, reqs, [0.0] * n_requests, ev)
+        sat_rate = n_requests / sat["wall_s"]
+        out["saturation"] = {"requests_per_s": sat_rate, "evals_per_s": sat["evals_per_s"],
+                             "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]}
+        for k, frac in enumerate((0.5, 0.8, 0.95)):
+            reqs = workload.make_proposal_stream(n_requests, 510 + k, len(ds))
+            arr = workload.poisson_arrivals(n_requests, frac * sat_rate, 520 + k)
+            _, summ = serving.run_stream(server, reqs, arr, ev)
+            st = summ.pop("stats")
+            summ.update({k2: st[k2] for k2 in ("max_in_flight", "max_queued", "budget_waits",
+                                               "peak_scratch_bytes", "completed")})
+            out[f"rate_{frac}"] = summ
+    finally:
+        server.close()
     return out
 
 
@@ -215,6 +290,10 @@ def main():
     }
     if not args.no_forms:
         result["precision_form"] = precision_form(osc, ctx, ds)
+    if not args.no_batch:
+        result["batched_form"] = batched_form(osc, ctx)
+    if not args.no_serve:
+        result["serving_form"] = serving_form(osc, ctx, args.serve_requests)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(s, args.cpu_events, args.cpu_events_1t)
         result["speedup_vs_cpu_all_cores"] = value / result["cpu_baseline"]["value"]

@@ -155,6 +155,113 @@ osc_status osc_profile_enable(osc_ctx* ctx, int on);
 osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
                             double* merge_kernel_ms, int64_t* merge_kernel_launches);
 
+/* ---- Batched form ---------------------------------------------------------
+ * Every parameter set x every sample of a list in one persistent kernel
+ * launch plus the histogram merge (the fitter evaluating many proposals, or
+ * one proposal against several samples).  Each (set, sample) histogram is
+ * bit-identical to osc_fill_pdf on that set and sample in the same
+ * precision, for every launch configuration. */
+typedef struct osc_batch osc_batch;
+
+typedef struct {
+    int32_t sets_per_item; /* parameter sets one wave evaluates per tile (1..64)   */
+    int32_t schedule;      /* 0: persistent waves taking tiles from an atomic queue;
+                              1: persistent waves striding over the tiles;
+                              2: one workgroup per tile                            */
+    int32_t waves_per_cu;  /* persistent grid = CUs x waves_per_cu, 0 = occupancy   */
+    int32_t use_graph;     /* 1: replay a captured HIP graph, 0: launch directly    */
+} osc_batch_config;
+
+/* Prepare a batched evaluation over n_samples (1..16) resident samples
+ * (device arrays as in osc_sample; they must stay valid and unchanged for
+ * the life of the batch), one binning and one precision, for up to max_sets
+ * parameter sets per run.  Allocates the device scratch (tile results of
+ * max_sets sets) and chooses a default configuration. */
+osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_samples,
+                            const osc_binning* binning, osc_precision precision, int32_t max_sets,
+                            osc_batch** out);
+
+/* Wait for the device and free the batch. NULL is accepted. */
+osc_status osc_batch_destroy(osc_batch* batch);
+
+osc_status osc_batch_get_config(const osc_batch* batch, osc_batch_config* cfg);
+osc_status osc_batch_set_config(osc_batch* batch, const osc_batch_config* cfg);
+
+/* Evaluate n_sets (1..max_sets) parameter sets on every sample: host
+ * precompute of the sets (Sec. 2.1), an asynchronous upload, one graph
+ * replay (kernel + merge) and a device copy of the histograms to hist_out
+ * (device, n_sets x n_samples x (nbins + 2) FP64, set-major).  Runs on
+ * `stream`; a batch serves one stream at a time.  The host array may be
+ * freed on return. */
+osc_status osc_batch_run(osc_batch* batch, const osc_params* sets, int32_t n_sets,
+                         double* hist_out, void* stream);
+
+/* Autotuner: time every candidate configuration (sets per item x schedule)
+ * on these parameter sets and keep the fastest.  With cache_path, a result
+ * recorded there for the same shape (tier, bins, samples, sets, log2 of the
+ * tile count) is reused without timing, and new results are appended.
+ * best_ms (nullable) receives the winning time, or -1 when cached.
+ * Blocks until the timing runs have finished. */
+osc_status osc_batch_tune(osc_batch* batch, const osc_params* sets, int32_t n_sets,
+                          const char* cache_path, double* best_ms, void* stream);
+
+/* ---- Serving form ----------------------------------------------------------
+ * A request loop for fitter proposals: each request is one parameter set on
+ * one resident sample in one precision tier.  Requests are queued first in,
+ * first out; a dispatcher thread admits the head of the queue when one of
+ * `slots` HIP streams is free and the request's device scratch fits in the
+ * remaining budget; admitted requests run concurrently.  A request's
+ * histogram is the same, bit for bit, as osc_fill_pdf of the same set,
+ * sample and tier, alone or in any mix. */
+typedef struct osc_server osc_server;
+
+typedef struct {
+    int32_t slots;                /* requests in flight at once (1..64)              */
+    int32_t queue_capacity;       /* pending requests before submit is refused        */
+    int64_t scratch_budget_bytes; /* device scratch shared by the requests in flight   */
+} osc_server_config;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, rejected;
+    int64_t in_flight, max_in_flight, queued, max_queued;
+    int64_t budget_waits;          /* times the queue head waited for scratch budget */
+    int64_t peak_scratch_bytes, scratch_in_use_bytes;
+} osc_server_stats;
+
+/* Start a server over n_samples resident samples (device arrays as in
+ * osc_sample, valid and unchanged for the server's life) and one binning.
+ * Allocates the scratch budget, the slot streams and pinned result buffers,
+ * and starts the dispatcher thread. */
+osc_status osc_server_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_samples,
+                             const osc_binning* binning, const osc_server_config* cfg,
+                             osc_server** out);
+
+/* Stop the dispatcher, wait for the requests in flight and free the server.
+ * Requests not yet admitted are dropped. NULL is accepted. */
+osc_status osc_server_destroy(osc_server* server);
+
+/* Queue one request; *ticket identifies it.  OSC_ERR_BUDGET when the queue
+ * is full or the request could never fit in the scratch budget;
+ * OSC_ERR_INVALID_ARG for an invalid parameter set or sample index. */
+osc_status osc_server_submit(osc_server* server, const osc_params* set, int32_t sample,
+                             osc_precision precision, uint64_t* ticket);
+
+/* Non-blocking: OSC_ERR_NOT_READY while the request runs; once done,
+ * copies the histogram (nbins + 2 FP64, host memory; nullable), the latency
+ * from submission to the histogram on the host and the time spent queued
+ * (seconds; nullable), forgets the ticket and returns the request's status. */
+osc_status osc_server_poll(osc_server* server, uint64_t ticket, double* hist, double* latency_s,
+                           double* queue_s);
+
+/* Blocking form of osc_server_poll. */
+osc_status osc_server_wait(osc_server* server, uint64_t ticket, double* hist, double* latency_s,
+                           double* queue_s);
+
+osc_status osc_server_get_stats(osc_server* server, osc_server_stats* out);
+
+/* Device scratch (bytes) one request on `sample` takes from the budget. */
+osc_status osc_server_request_bytes(const osc_server* server, int32_t sample, int64_t* bytes);
+
 /* Constants of the reduction contract: W lanes per tile and K events per
  * lane.  Either pointer may be NULL. */
 void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events);

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/osc.h"
+#include "osc_host_common.h"
 #include "osc_internal.h"
 #include "osc_launch.h"
 
@@ -33,18 +34,18 @@ double matter_constant()
     return 2.0 * std::sqrt(2.0) * (kFermiGeV * 1.0e-18) * ne_ev3 * 1.0e9;
 }
 
-bool finite(double x) { return std::isfinite(x); }
+bool is_finite(double x) { return std::isfinite(x); }
 
 bool params_ok(const osc_params& p)
 {
     const double s[3] = {p.sin2_th12, p.sin2_th23, p.sin2_th13};
     for (double v : s)
-        if (!finite(v) || v < 0.0 || v > 1.0) return false;
-    if (!finite(p.dm2_21) || !(p.dm2_21 > 0.0)) return false;
-    if (!finite(p.dm2_32) || p.dm2_32 == 0.0) return false;
+        if (!is_finite(v) || v < 0.0 || v > 1.0) return false;
+    if (!is_finite(p.dm2_21) || !(p.dm2_21 > 0.0)) return false;
+    if (!is_finite(p.dm2_32) || p.dm2_32 == 0.0) return false;
     const double dm31 = p.dm2_32 + p.dm2_21;
-    if (!finite(dm31) || dm31 == 0.0) return false;
-    if (!finite(p.delta_cp)) return false;
+    if (!is_finite(dm31) || dm31 == 0.0) return false;
+    if (!is_finite(p.delta_cp)) return false;
     return true;
 }
 
@@ -67,8 +68,10 @@ void mixing_matrix(const osc_params& p, cplx U[3][3])
     U[2][2] = c23 * c13;
 }
 
+}  // namespace
+
 // Parameter-only quantities of one set for the kernels.
-osc::SetConsts set_consts(const osc_params& p)
+osc::SetConsts osc::host::set_consts(const osc_params& p)
 {
     cplx U[3][3];
     mixing_matrix(p, U);
@@ -110,6 +113,8 @@ osc::SetConsts set_consts(const osc_params& p)
     return sc;
 }
 
+namespace {
+
 struct Scratch {
     void* ptr = nullptr;
     size_t cap = 0;
@@ -147,7 +152,7 @@ void drop_profile(osc_ctx* ctx)
 {
     for (ProfRec& r : ctx->prof) {
         for (hipEvent_t e : {r.start, r.mid, r.end})
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
     }
     ctx->prof.clear();
 }
@@ -160,7 +165,7 @@ ProfRec* prof_begin(osc_ctx* ctx, hipStream_t stream)
     if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.mid) != hipSuccess ||
         hipEventCreate(&r.end) != hipSuccess || hipEventRecord(r.start, stream) != hipSuccess) {
         for (hipEvent_t e : {r.start, r.mid, r.end})
-            if (e) hipEventDestroy(e);
+            if (e) (void)hipEventDestroy(e);
         return nullptr;
     }
     ctx->prof.push_back(r);
@@ -169,7 +174,7 @@ ProfRec* prof_begin(osc_ctx* ctx, hipStream_t stream)
 
 void prof_mark(hipEvent_t ev, hipStream_t stream)
 {
-    if (ev) hipEventRecord(ev, stream);
+    if (ev) (void)hipEventRecord(ev, stream);
 }
 
 // Scratch for one call on `stream`: slots are used round-robin; a reused
@@ -192,9 +197,6 @@ osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scrat
             s.ptr = nullptr;
             return OSC_ERR_OUT_OF_MEMORY;
         }
-        // the merge kernel's arrival counter starts at zero (the kernel
-        // resets it after every use)
-        if (hipMemset(s.ptr, 0, osc::kMergeCounterBytes) != hipSuccess) return OSC_ERR_DEVICE;
         s.cap = want;
         s.recorded = false;
     } else if (s.recorded) {
@@ -211,12 +213,14 @@ osc_status release_scratch(Scratch* s, hipStream_t stream)
     return OSC_OK;
 }
 
-bool sample_ok(const osc_sample* s, bool needs_hist_inputs)
+}  // namespace
+
+bool osc::host::sample_ok(const osc_sample* s, bool needs_hist_inputs)
 {
     if (!s || s->n < 0 || s->n > osc::kMaxEvents) return false;
-    if (!finite(s->L_km) || s->L_km < 0.0) return false;
-    if (!finite(s->rho_gcc) || s->rho_gcc < 0.0) return false;
-    if (!finite(s->Ye) || s->Ye < 0.0 || s->Ye > 1.0) return false;
+    if (!is_finite(s->L_km) || s->L_km < 0.0) return false;
+    if (!is_finite(s->rho_gcc) || s->rho_gcc < 0.0) return false;
+    if (!is_finite(s->Ye) || s->Ye < 0.0 || s->Ye > 1.0) return false;
     if (s->n > 0) {
         if (!s->e_true || !s->flags) return false;
         if (needs_hist_inputs && (!s->weight || !s->e_reco)) return false;
@@ -224,24 +228,54 @@ bool sample_ok(const osc_sample* s, bool needs_hist_inputs)
     return true;
 }
 
-bool binning_ok(const osc_ctx* ctx, const osc_binning* b)
+bool osc::host::binning_ok(const osc_ctx* ctx, const osc_binning* b)
 {
     if (!b || b->nbins < 1 || b->nbins > ctx->max_nbins) return false;
-    if (!finite(b->lo) || !finite(b->hi) || !(b->lo < b->hi)) return false;
+    if (!is_finite(b->lo) || !is_finite(b->hi) || !(b->lo < b->hi)) return false;
     const double wb = (b->hi - b->lo) / double(b->nbins);
-    return finite(wb) && wb > 0.0;
+    return is_finite(wb) && wb > 0.0;
 }
 
-osc::PathConsts path_consts(const osc_sample* s)
+osc::PathConsts osc::host::path_consts(const osc_sample* s)
 {
     return osc::PathConsts{matter_constant() * s->Ye * s->rho_gcc, phase_constant() * s->L_km};
 }
 
-osc::BinConsts bin_consts(const osc_binning* b)
+osc::BinConsts osc::host::bin_consts(const osc_binning* b)
 {
     const double wb = (b->hi - b->lo) / double(b->nbins);
     return osc::BinConsts{b->lo, wb, 1.0 / wb, b->nbins};
 }
+
+int osc::host::ctx_device(const osc_ctx* ctx) { return ctx->device; }
+
+size_t osc::host::fill_scratch_bytes(int64_t n, int nbins)
+{
+    const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
+    return osc::merge_scratch_bytes(osc::plan_merge(&tiles, 1, nbins + 2), 1);
+}
+
+hipError_t osc::host::enqueue_fill(const osc::SetConsts& sc, const osc_sample* sample,
+                                   const osc_binning* binning, bool mixed, double* scratch,
+                                   double* hist_out, double* p_out, hipStream_t stream)
+{
+    const osc::BinConsts bc = bin_consts(binning);
+    const int64_t tiles = (sample->n + osc::kTileEvents - 1) / osc::kTileEvents;
+    const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
+    hipError_t e = osc::launch_tiles(1, p_out != nullptr, mixed, sc, path_consts(sample), bc,
+                                     sample->n, sample->e_true, sample->flags, sample->weight,
+                                     sample->e_reco, nullptr, p_out, scratch, stream);
+    if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
+    return e;
+}
+
+namespace {
+
+using osc::host::bin_consts;
+using osc::host::binning_ok;
+using osc::host::path_consts;
+using osc::host::sample_ok;
+using osc::host::set_consts;
 
 // Tile partials + merge for one histogram on `stream`.
 osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
@@ -251,14 +285,17 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
                     double* hist_out, hipStream_t stream)
 {
     const int nbt = bc.nb + 2;
+    const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
+    const osc::MergePlan plan = osc::plan_merge(&tiles, 1, nbt);
     Scratch* s = nullptr;
-    osc_status st = acquire_scratch(ctx, osc::merge_scratch_bytes(n, nbt), stream, &s);
+    osc_status st = acquire_scratch(ctx, osc::merge_scratch_bytes(plan, 1), stream, &s);
     if (st != OSC_OK) return st;
+    double* scratch = static_cast<double*>(s->ptr);
     ProfRec* pr = prof_begin(ctx, stream);
     hipError_t e = osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags, weight,
-                                     e_reco, value, p_out, osc::scratch_partials(s->ptr), stream);
+                                     e_reco, value, p_out, scratch, stream);
     if (pr) prof_mark(pr->mid, stream);
-    if (e == hipSuccess) e = osc::launch_merge(s->ptr, n, nbt, hist_out, stream);
+    if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
     if (pr) prof_mark(pr->end, stream);
     st = release_scratch(s, stream);
     if (e != hipSuccess) return OSC_ERR_DEVICE;
@@ -306,7 +343,7 @@ osc_status osc_destroy(osc_ctx* ctx)
 {
     if (!ctx) return OSC_OK;
     osc_status st = OSC_OK;
-    hipSetDevice(ctx->device);
+    (void)hipSetDevice(ctx->device);
     drop_profile(ctx);
     for (Scratch& s : ctx->scratch) {
         if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
@@ -358,7 +395,7 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, dou
                                            nullptr, nullptr, p_out, nullptr, hs);
     if (pr) {
         prof_mark(pr->mid, hs);
-        hipEventDestroy(pr->end);
+        (void)hipEventDestroy(pr->end);
         pr->end = nullptr;
     }
     return device_status(e);

@@ -1,0 +1,31 @@
+// Host-side helpers of libosc shared by the plain entry points and the
+// batched form (defined in osc_host.hip).
+#pragma once
+
+#include "../../include/osc.h"
+#include "osc_internal.h"
+
+namespace osc {
+namespace host {
+
+// Parameter-only quantities of one set (mixing matrix, flavour-basis
+// vacuum mass matrix and its square, cubic constants, channel table).
+SetConsts set_consts(const osc_params& p);
+PathConsts path_consts(const osc_sample* s);
+BinConsts bin_consts(const osc_binning* b);
+bool sample_ok(const osc_sample* s, bool needs_hist_inputs);
+bool binning_ok(const osc_ctx* ctx, const osc_binning* b);
+int ctx_device(const osc_ctx* ctx);
+
+// Device scratch one osc_fill_pdf-style histogram of n events needs.
+size_t fill_scratch_bytes(int64_t n, int nbins);
+
+// Enqueues the per-event kernel and the merge of one histogram on `stream`
+// with caller-provided scratch (fill_scratch_bytes).  Arguments are assumed
+// validated.
+hipError_t enqueue_fill(const SetConsts& sc, const osc_sample* sample, const osc_binning* binning,
+                        bool mixed, double* scratch, double* hist_out, double* p_out,
+                        hipStream_t stream);
+
+}  // namespace host
+}  // namespace osc

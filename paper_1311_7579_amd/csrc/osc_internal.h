@@ -14,14 +14,29 @@ constexpr int kTileEvents = kTileLanes * kLaneEvents;
 
 // Largest event count accepted.
 constexpr int64_t kMaxEvents = int64_t(1) << 32;
-// Histogram merge: 256-thread blocks, each reducing an aligned chunk of
-// kMergeChunkTiles tile results per bin.  The scratch buffer starts with the
-// merge's arrival counter (kMergeCounterBytes, zeroed when the buffer is
-// allocated, reset by the kernel after every use), then holds the tile
-// results (bin-major within each chunk), then the chunk results.
+// Histogram merge: launches of 256-thread blocks, each reducing an aligned
+// chunk of kMergeChunkTiles rows (tile results, then chunk results) per bin,
+// level by level until one row per histogram is left.  Rows are stored
+// bin-major within each chunk (partial_index).
 constexpr int kMergeThreads = 256;
 constexpr int kMergeChunkTiles = 128;
-constexpr size_t kMergeCounterBytes = 256;
+constexpr int kMaxBatchSamples = 16;
+
+// One level of the merge for n_samples samples (x any number of parameter
+// sets, one set per grid row): sample s has rows[s] input rows stored from
+// row 128 * chunk0[s] of the set's input region and produces
+// ceil(rows[s] / 128) (at least one) output rows, stored from row
+// out_row0[s] of the set's output region.  The final level writes
+// hist[set][sample][bin] instead.
+struct MergeLevel {
+    int32_t n_samples;
+    int32_t nbt;
+    int64_t total_chunks;                 // blocks per set
+    int64_t set_stride_in, set_stride_out;
+    int64_t rows[kMaxBatchSamples];
+    int64_t chunk0[kMaxBatchSamples];
+    int64_t out_row0[kMaxBatchSamples];
+};
 
 // Position of the result of (tile, bin) among the tile results.
 __host__ __device__ inline int64_t partial_index(int64_t tile, int bin, int nbt)

@@ -9,6 +9,10 @@
 // fixed binary tree; a merge kernel adds the tile results per bin in a
 // fixed binary tree.  No atomics: the bits of the histogram do not depend
 // on the launch shape.
+#include <algorithm>
+#include <vector>
+
+#include "osc_device.h"
 #include "osc_internal.h"
 #include "osc_launch.h"
 
@@ -16,375 +20,7 @@ namespace osc {
 
 namespace {
 
-constexpr int kPrefetch = 4;   // events in flight ahead of the one computed
-
-// ---------------------------------------------------------------------------
-// FP64 sine and cosine of a phase (|x| up to ~1e6 rad).
-// Cody-Waite reduction by pi/2 with a two-term constant (FMA form), then
-// the Taylor series of sin to r^15 and of cos to r^16 on |r| <= pi/4
-// (truncation below 5e-17), then the quadrant rotation.
-// ---------------------------------------------------------------------------
-constexpr double kTwoOverPi = 0.63661977236758134308;
-constexpr double kPiOver2Hi = 1.5707963267948966192;        // fl(pi/2)
-constexpr double kPiOver2Lo = 6.123233995736766036e-17;      // fl(pi/2 - fl(pi/2))
-
-// (-1)^k / (2k+1)!  and  (-1)^k / (2k)!
-constexpr double kS1 = -1.0 / 6.0;
-constexpr double kS2 = 1.0 / 120.0;
-constexpr double kS3 = -1.0 / 5040.0;
-constexpr double kS4 = 1.0 / 362880.0;
-constexpr double kS5 = -1.0 / 39916800.0;
-constexpr double kS6 = 1.0 / 6227020800.0;
-constexpr double kS7 = -1.0 / 1307674368000.0;
-constexpr double kC1 = -1.0 / 2.0;
-constexpr double kC2 = 1.0 / 24.0;
-constexpr double kC3 = -1.0 / 720.0;
-constexpr double kC4 = 1.0 / 40320.0;
-constexpr double kC5 = -1.0 / 3628800.0;
-constexpr double kC6 = 1.0 / 479001600.0;
-constexpr double kC7 = -1.0 / 87178291200.0;
-constexpr double kC8 = 1.0 / 20922789888000.0;
-
-__device__ __forceinline__ double flip_sign(double v, uint32_t sign_bit)
-{
-    return __hiloint2double(__double2hiint(v) ^ int(sign_bit), __double2loint(v));
-}
-
-__device__ __forceinline__ void phase_sincos(double x, double& sn, double& cs)
-{
-    const double n = __builtin_rint(x * kTwoOverPi);
-    double r = fma(-n, kPiOver2Hi, x);
-    r = fma(-n, kPiOver2Lo, r);
-    const double z = r * r;
-    double ps = fma(z, kS7, kS6);
-    ps = fma(z, ps, kS5);
-    ps = fma(z, ps, kS4);
-    ps = fma(z, ps, kS3);
-    ps = fma(z, ps, kS2);
-    ps = fma(z, ps, kS1);
-    const double s = fma(r * z, ps, r);
-    double pc = fma(z, kC8, kC7);
-    pc = fma(z, pc, kC6);
-    pc = fma(z, pc, kC5);
-    pc = fma(z, pc, kC4);
-    pc = fma(z, pc, kC3);
-    pc = fma(z, pc, kC2);
-    pc = fma(z, pc, kC1);
-    const double c = fma(z, pc, 1.0);
-    // quadrant q = n mod 4: sin = (s, c, -s, -c)[q], cos = (c, -s, -c, s)[q]
-    const int q = int(n);
-    const bool swap = (q & 1) != 0;
-    const uint32_t sgn_s = uint32_t(q << 30) & 0x80000000u;
-    const uint32_t sgn_c = uint32_t((q + 1) << 30) & 0x80000000u;
-    sn = flip_sign(swap ? c : s, sgn_s);
-    cs = flip_sign(swap ? s : c, sgn_c);
-}
-
-// Mixed tier: the phase is reduced modulo 2 pi in FP64 (two-term
-// Cody-Waite), the remainder in revolutions is rounded to FP32 and the FP32
-// hardware sine and cosine (argument in revolutions) finish the job.
-constexpr double kInvTwoPi = 0.15915494309189533577;
-constexpr double kTwoPiHi = 6.283185307179586232;             // fl(2 pi)
-constexpr double kTwoPiLo = 2.4492935982947064e-16;           // fl(2 pi - fl(2 pi))
-
-__device__ __forceinline__ void phase_sincos_mixed(double x, float& sn, float& cs)
-{
-    const double n = __builtin_rint(x * kInvTwoPi);
-    double r = fma(-n, kTwoPiHi, x);
-    r = fma(-n, kTwoPiLo, r);
-    const float rev = float(r * kInvTwoPi);
-    sn = __builtin_amdgcn_sinf(rev);
-    cs = __builtin_amdgcn_cosf(rev);
-}
-
-// 1/y to within a few ulp: hardware reciprocal estimate + two
-// Newton-Raphson corrections (y normal, not huge).
-__device__ __forceinline__ double recip(double y)
-{
-    double r = __builtin_amdgcn_rcp(y);
-    double e = fma(-y, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-y, r, 1.0);
-    return fma(r, e, r);
-}
-
-// arccos on [-1, 1] in FP32: Abramowitz & Stegun 4.4.46 on |x| (error
-// <= 2.2e-8 rad) and acos(-x) = pi - acos(x).
-__device__ __forceinline__ float acos_f32(float x)
-{
-    const float ax = __builtin_fabsf(x);
-    float p = -0.0012624911f;
-    p = __builtin_fmaf(p, ax, 0.0066700901f);
-    p = __builtin_fmaf(p, ax, -0.0170881256f);
-    p = __builtin_fmaf(p, ax, 0.0308918810f);
-    p = __builtin_fmaf(p, ax, -0.0501743046f);
-    p = __builtin_fmaf(p, ax, 0.0889789874f);
-    p = __builtin_fmaf(p, ax, -0.2145988016f);
-    p = __builtin_fmaf(p, ax, 1.5707963050f);
-    const float r = __builtin_amdgcn_sqrtf(1.0f - ax) * p;
-    return x < 0.0f ? 3.14159265358979f - r : r;
-}
-
-// Roots of f(x) = x^3 - tr x^2 + c1 x - det (three real roots: the matrix
-// is Hermitian).  Two roots are seeded in FP32 from the trigonometric
-// solution x = tr/3 + (2/3) sqrt(p) cos(theta - 2 pi k / 3),
-// theta = acos(q / (2 p^1.5)) / 3 (p = tr^2 - 3 c1, q = 2 tr^3 - 9 tr c1 +
-// 27 det), each refined in FP64 by one Halley and one Newton step on f; the
-// third root follows from the trace.
-__device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
-                                            double& l0, double& l1, double& l2)
-{
-    const double p = fma(tr, tr, -3.0 * c1);
-    const double q = fma(tr, fma(2.0 * tr, tr, -9.0 * c1), 27.0 * det);
-    const float pf = float(p), qf = float(q);
-    const float spf = __builtin_amdgcn_sqrtf(pf);
-    float rf = qf * __builtin_amdgcn_rcpf(2.0f * pf * spf);
-    rf = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, rf));
-    // theta in revolutions for the hardware cosine: acos(r) / (3 * 2 pi)
-    const float th = acos_f32(rf) * 0.053051647697298445f;
-    const double k = double((2.0f / 3.0f) * spf);
-    const double t3 = tr * (1.0 / 3.0);
-    double x[2];
-    x[0] = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
-    x[1] = fma(k, double(__builtin_amdgcn_cosf(th - 0.33333333f)), t3);
-    const double tr2 = 2.0 * tr;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        double y = x[j];
-        // Halley: y -= 2 f f' / (2 f'^2 - f f'')
-        double f = fma(fma(y - tr, y, c1), y, -det);
-        double fp = fma(y, fma(3.0, y, -tr2), c1);
-        const double fpp = fma(6.0, y, -tr2);
-        y -= (f * fp) * recip(fma(fp, fp, -0.5 * f * fpp));
-        // Newton: y -= f / f'
-        f = fma(fma(y - tr, y, c1), y, -det);
-        fp = fma(y, fma(3.0, y, -tr2), c1);
-        y -= f * recip(fp);
-        x[j] = y;
-    }
-    l0 = x[0];
-    l1 = x[1];
-    l2 = (tr - l0) - l1;
-}
-
-// P(alpha -> beta) of one event.  The evolution operator over L is
-// sum_k exp(-i phi_k) X_k with the spectral projectors
-// X_k = (M - l_j)(M - l_l) / ((l_k - l_j)(l_k - l_l)); the common phase
-// exp(-i phi_0) drops out of |.|^2, so only the differences phi_k - phi_0
-// are formed.
-template <bool MIXED>
-__device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* tab,
-                                             double kA, double kL, double E, uint32_t f)
-{
-    const uint32_t a = f & 3u, b = (f >> 2) & 3u;
-    const bool valid = (a < 3u) && (b < 3u) && (f < 32u);
-    const uint32_t idx = valid ? (b * 3u + a) : 0u;
-    const double s = ((f >> 4) & 1u) ? -1.0 : 1.0;
-    const Chan c = tab[idx];
-    const double A = s * kA * E;
-    const double dee = (idx == 0u) ? 1.0 : 0.0;          // alpha = beta = e
-    const double dba = (a == b) ? 1.0 : 0.0;
-
-    // amplitude inputs: M_ba and (M^2)_ba (conjugated for antineutrinos)
-    const double mre = fma(A, dee, c.m_re);
-    const double mim = s * c.m_im;
-    const double m2re = fma(A, fma(A, dee, c.g_re), c.m2_re);
-    const double m2im = s * fma(A, c.g_im, c.m2_im);
-
-    // matter eigenvalues (FP64 in every tier)
-    double l0, l1, l2;
-    cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA, l0, l1, l2);
-
-    const double d01 = l0 - l1, d02 = l0 - l2, d12 = l1 - l2;
-    const double Q = d01 * d02 * d12;
-    const double R = recip(E * Q);
-    const double invE = Q * R, invQ = E * R;
-    const double ph = kL * invE;
-    // numerator coefficients: N_k = (M^2)_ba - (l_j + l_l) M_ba + l_j l_l [a = b]
-    const double u0 = l1 + l2, v0 = l1 * l2;
-    const double u1 = l0 + l2, v1 = l0 * l2;
-    const double u2 = l0 + l1, v2 = l0 * l1;
-    const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
-
-    double P;
-    if constexpr (!MIXED) {
-        double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, s2, c2);   // phi_2 - phi_0
-        const double x0r = fma(v0, dba, fma(-u0, mre, m2re)) * iD0;
-        const double x0i = fma(-u0, mim, m2im) * iD0;
-        const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
-        const double x1i = fma(-u1, mim, m2im) * iD1;
-        const double x2r = fma(v2, dba, fma(-u2, mre, m2re)) * iD2;
-        const double x2i = fma(-u2, mim, m2im) * iD2;
-        // S' = X0 + exp(-i dphi1) X1 + exp(-i dphi2) X2
-        const double sr = x0r + c1 * x1r + s1 * x1i + c2 * x2r + s2 * x2i;
-        const double si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
-        P = sr * sr + si * si;
-    } else {
-        float s1, c1, s2, c2;
-        phase_sincos_mixed(-d01 * ph, s1, c1);
-        phase_sincos_mixed(-d02 * ph, s2, c2);
-        // amplitude assembly in FP32 from FP32-rounded inputs
-        const float fmre = float(mre), fmim = float(mim), fm2re = float(m2re), fm2im = float(m2im);
-        const float fdba = float(dba);
-        const float fu0 = float(u0), fu1 = float(u1), fu2 = float(u2);
-        const float fv0 = float(v0), fv1 = float(v1), fv2 = float(v2);
-        const float fi0 = float(iD0), fi1 = float(iD1), fi2 = float(iD2);
-        const float x0r = __builtin_fmaf(fv0, fdba, __builtin_fmaf(-fu0, fmre, fm2re)) * fi0;
-        const float x0i = __builtin_fmaf(-fu0, fmim, fm2im) * fi0;
-        const float x1r = __builtin_fmaf(fv1, fdba, __builtin_fmaf(-fu1, fmre, fm2re)) * fi1;
-        const float x1i = __builtin_fmaf(-fu1, fmim, fm2im) * fi1;
-        const float x2r = __builtin_fmaf(fv2, fdba, __builtin_fmaf(-fu2, fmre, fm2re)) * fi2;
-        const float x2i = __builtin_fmaf(-fu2, fmim, fm2im) * fi2;
-        const float sr = x0r + c1 * x1r + s1 * x1i + c2 * x2r + s2 * x2i;
-        const float si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
-        P = double(sr * sr + si * si);
-    }
-    return valid ? P : __builtin_nan("");
-}
-
-// Bin of x: floor(fl(fl(x - lo) / wb)) with under/overflow entries.  The
-// quotient is first formed as fl(x - lo) * fl(1 / wb); that is within 3 ulp
-// of the correctly rounded quotient, so the floors agree unless the product
-// lies within 2^-40 of an integer (the bound for quotients below 2^11).
-// Such lanes are flagged and redone with the correctly rounded division.
-__device__ __forceinline__ double bin_floor_fast(double x, const BinConsts& bc, bool& edge)
-{
-    const double d = x - bc.lo;
-    const double q = d * bc.inv_wb;
-    const double k = __builtin_floor(q);
-    const double fr = q - k;
-    edge = (fr < 0x1p-40 || fr > 1.0 - 0x1p-40) && (k > -3.0) && (k < bc.nb + 2.0);
-    return k;
-}
-
-__device__ __forceinline__ double bin_floor_exact(double x, const BinConsts& bc)
-{
-    return __builtin_floor((x - bc.lo) / bc.wb);
-}
-
-__device__ __forceinline__ int bin_index(double k, const BinConsts& bc)
-{
-    return (k < 0.0) ? bc.nb : ((k < double(bc.nb)) ? int(k) : bc.nb + 1);
-}
-
-// Lane-private histogram slot: bin-major rows of 64 lanes, the lane index
-// XOR-swizzled by the bin so that both the per-lane accumulation and the
-// per-bin transposed reads spread over the LDS banks.
-__device__ __forceinline__ int hslot(int bin, int lane)
-{
-    return bin * kTileLanes + (lane ^ (bin & 31));
-}
-
-// complete binary tree over the 64 lane sums of one bin
-template <int N, int J0>
-__device__ __forceinline__ double lane_tree(const double* h, int bin)
-{
-    if constexpr (N == 1) {
-        return h[hslot(bin, J0)];
-    } else {
-        const double left = lane_tree<N / 2, J0>(h, bin);
-        const double right = lane_tree<N / 2, J0 + N / 2>(h, bin);
-        return left + right;
-    }
-}
-
-enum Mode { kReweight = 0, kPdf = 1, kHist = 2 };
-
-struct EventIn {
-    double e;     // true energy (or the given value in kHist mode)
-    double w;
-    double x;
-    uint32_t f;
-};
-
-template <int MODE, bool FULL>
-__device__ __forceinline__ EventIn load_event(int64_t i, int64_t n, const double* e_true,
-                                              const uint8_t* flags, const double* weight,
-                                              const double* e_reco, const double* value)
-{
-    EventIn v;
-    const bool in = FULL || i < n;
-    v.e = in ? (MODE == kHist ? value[i] : e_true[i]) : 1.0;
-    v.f = (MODE != kHist && in) ? uint32_t(flags[i]) : 0u;
-    v.w = (MODE != kReweight && in) ? weight[i] : 0.0;
-    v.x = (MODE != kReweight && in) ? e_reco[i] : 0.0;
-    return v;
-}
-
-// One group of kPrefetch events of a lane: the probabilities are computed
-// in one straight-line block (no guards: lanes past the end of the sample
-// hold dummy inputs), then stored, binned and accumulated in ascending m.
-template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
-__device__ __forceinline__ void tile_group(const SetConsts& sc, const Chan* tab,
-                                           const PathConsts& pc, const BinConsts& bc,
-                                           double* hist, int lane, int64_t i0, int64_t n,
-                                           const EventIn (&ev)[kPrefetch], double* p_out)
-{
-    double P[kPrefetch], k[kPrefetch];
-    bool edge[kPrefetch];
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
-        P[j] = (MODE != kHist) ? event_prob<MIXED>(sc, tab, pc.kA, pc.kL, ev[j].e, ev[j].f)
-                               : ev[j].e;
-        k[j] = (MODE != kReweight) ? bin_floor_fast(ev[j].x, bc, edge[j]) : 0.0;
-    }
-    if (WRITE_P) {
-#pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
-            const int64_t i = i0 + int64_t(j) * kTileLanes;
-            if (FULL || i < n) p_out[i] = P[j];
-        }
-    }
-    if (MODE == kReweight) return;
-    bool any_edge = false;
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) any_edge |= edge[j];
-    if (__builtin_expect(any_edge, 0)) {
-#pragma unroll
-        for (int j = 0; j < kPrefetch; ++j)
-            if (edge[j]) k[j] = bin_floor_exact(ev[j].x, bc);
-    }
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
-        const int64_t i = i0 + int64_t(j) * kTileLanes;
-        if (FULL || i < n) {
-#pragma clang fp contract(off)
-            const double cval = ev[j].w * P[j];            // rounded, never fused
-            const int slot = hslot(bin_index(k[j], bc), lane);
-            hist[slot] = hist[slot] + cval;                // ascending m per lane
-        }
-    }
-}
-
-template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
-__device__ __forceinline__ void tile_events(const SetConsts& sc, const Chan* tab,
-                                            const PathConsts& pc, const BinConsts& bc,
-                                            double* hist, int lane, int64_t base, int64_t n,
-                                            const double* e_true, const uint8_t* flags,
-                                            const double* weight, const double* e_reco,
-                                            const double* value, double* p_out)
-{
-    EventIn ring[kPrefetch];
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j)
-        ring[j] = load_event<MODE, FULL>(base + int64_t(j) * kTileLanes, n, e_true, flags,
-                                         weight, e_reco, value);
-    for (int m0 = 0; m0 < kLaneEvents; m0 += kPrefetch) {
-        EventIn cur[kPrefetch];
-#pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) cur[j] = ring[j];
-        if (m0 + kPrefetch < kLaneEvents) {
-#pragma unroll
-            for (int j = 0; j < kPrefetch; ++j)
-                ring[j] = load_event<MODE, FULL>(base + int64_t(m0 + kPrefetch + j) * kTileLanes,
-                                                 n, e_true, flags, weight, e_reco, value);
-        }
-        tile_group<MODE, WRITE_P, FULL, MIXED>(sc, tab, pc, bc, hist, lane,
-                                        base + int64_t(m0) * kTileLanes, n, cur, p_out);
-    }
-}
+using namespace dev;
 
 template <int MODE, bool WRITE_P, bool MIXED = false>
 __global__ __launch_bounds__(kTileLanes) void tile_kernel(
@@ -410,9 +46,7 @@ __global__ __launch_bounds__(kTileLanes) void tile_kernel(
                 for (int a = 0; a < 3; ++a) tab[b * 3 + a] = sc.ch[(b << 2) | a];
         }
     }
-    if (MODE != kReweight) {
-        for (int bin = 0; bin < nbt; ++bin) hist[hslot(bin, lane)] = 0.0;
-    }
+    if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
     if ((tile + 1) * kTileEvents <= n)
@@ -424,87 +58,16 @@ __global__ __launch_bounds__(kTileLanes) void tile_kernel(
 
     if (MODE != kReweight) {
         __syncthreads();
-        for (int bin = lane; bin < nbt; bin += kTileLanes)
-            partial[partial_index(tile, bin, nbt)] = lane_tree<kTileLanes, 0>(hist, bin);
+        tile_write(hist, lane, nbt, tile, partial);
     }
 }
 
-// Adjacent-pair tree across the 64 lanes of a wave (xor butterfly: both
-// partners of a pair form the same sum), result in every lane.
-__device__ __forceinline__ double wave_tree(double v)
+template <bool FINAL>
+__global__ __launch_bounds__(kMergeThreads) void merge_level_kernel(MergeLevel L,
+                                                                   const double* __restrict__ in,
+                                                                   double* __restrict__ out)
 {
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) v = v + __shfl_xor(v, s, 64);
-    return v;
-}
-
-// Complete binary tree over the kMergeChunkTiles values of one histogram
-// entry held contiguously at src (entries at or beyond `count` are +0.0):
-// lane l adds entries 2l and 2l + 1, the wave butterfly does the rest.
-__device__ __forceinline__ double chunk_sum(const double* __restrict__ src, int64_t first,
-                                            int64_t count, int lane)
-{
-    const int64_t e = first + 2 * lane;
-    const double a = e < count ? src[2 * lane] : 0.0;
-    const double b = e + 1 < count ? src[2 * lane + 1] : 0.0;
-    return wave_tree(a + b);
-}
-
-// Merge of the tile results.  Tile results sit bin-major within chunks of
-// kMergeChunkTiles tiles (partial_index).  Block c reduces chunk c: each
-// wave takes bins w, w + 4, ... and forms the chunk's complete tree per
-// bin; results go to level[bin * chunks + c].  The last block to arrive
-// (arrival counter, device-scope fences) reduces the chunk results of each
-// bin in aligned groups of kMergeChunkTiles, level by level, writes the
-// histogram and resets the counter for the next launch.
-__global__ __launch_bounds__(kMergeThreads) void merge_kernel(
-    const double* __restrict__ partial, int64_t ntiles, int64_t chunks, int nbt,
-    double* __restrict__ level, unsigned* __restrict__ counter, double* __restrict__ hist_out)
-{
-    __shared__ int is_last;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWaves = kMergeThreads / 64;
-    const int64_t c = blockIdx.x;
-    const double* chunk_base = partial + c * int64_t(nbt) * kMergeChunkTiles;
-    for (int b0 = wave; b0 < nbt; b0 += 4 * kWaves) {
-        double r[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + j * kWaves;
-            r[j] = b < nbt ? chunk_sum(chunk_base + int64_t(b) * kMergeChunkTiles,
-                                       c * kMergeChunkTiles, ntiles, lane)
-                           : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + j * kWaves;
-            if (lane == 0 && b < nbt) level[int64_t(b) * chunks + c] = r[j];
-        }
-    }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) is_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-
-    // chunk results of bin b: level[b * chunks + 0 .. count)
-    int64_t count = chunks;
-    while (count > 1) {
-        const int64_t groups = (count + kMergeChunkTiles - 1) / kMergeChunkTiles;
-        for (int64_t g = 0; g < groups; ++g) {
-            for (int b = wave; b < nbt; b += kWaves) {
-                const double v = chunk_sum(level + int64_t(b) * chunks + g * kMergeChunkTiles,
-                                           g * kMergeChunkTiles, count, lane);
-                // group g writes entry g, which only group 0 (already done) reads
-                if (lane == 0) level[int64_t(b) * chunks + g] = v;
-            }
-            __syncthreads();
-        }
-        count = groups;
-    }
-    for (int b = threadIdx.x; b < nbt; b += blockDim.x) hist_out[b] = level[int64_t(b) * chunks];
-    if (threadIdx.x == 0) *counter = 0u;
+    merge_level_block<FINAL>(L, in, out);
 }
 
 }  // namespace
@@ -537,24 +100,71 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
     return hipGetLastError();
 }
 
-size_t merge_scratch_bytes(int64_t n, int nbt)
+MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt)
 {
-    const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
-    const int64_t chunks = ntiles > 0 ? (ntiles + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
-    return kMergeCounterBytes +
-           size_t(chunks * kMergeChunkTiles + chunks) * size_t(nbt) * sizeof(double);
+    MergePlan p;
+    p.nbt = nbt;
+    p.n_samples = n_samples;
+    std::vector<int64_t> rows(tiles, tiles + n_samples);
+    int64_t level_max = 0;
+    bool first = true;
+    for (;;) {
+        MergeLevel L{};
+        L.n_samples = n_samples;
+        L.nbt = nbt;
+        int64_t chunks = 0, out_rows = 0;
+        bool final_level = true;
+        for (int s = 0; s < n_samples; ++s) {
+            const int64_t ch = rows[s] > kMergeChunkTiles ? (rows[s] + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
+            L.rows[s] = rows[s];
+            L.chunk0[s] = chunks;
+            L.out_row0[s] = out_rows * kMergeChunkTiles;
+            chunks += ch;
+            out_rows += ch > kMergeChunkTiles ? (ch + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
+            if (ch > 1) final_level = false;
+            rows[s] = ch;
+        }
+        L.total_chunks = chunks;
+        L.set_stride_in = chunks * kMergeChunkTiles * nbt;
+        L.set_stride_out = final_level ? 0 : out_rows * kMergeChunkTiles * nbt;
+        if (first) p.tile_set_stride = L.set_stride_in;
+        else level_max = std::max(level_max, L.set_stride_in);
+        if (!final_level) level_max = std::max(level_max, L.set_stride_out);
+        first = false;
+        p.levels.push_back(L);
+        if (final_level) break;
+    }
+    p.level_set_stride = level_max;
+    return p;
 }
 
-hipError_t launch_merge(void* scratch, int64_t n, int nbt, double* hist_out, hipStream_t stream)
+size_t merge_scratch_bytes(const MergePlan& p, int64_t n_sets)
 {
-    const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
-    const int64_t chunks = ntiles > 0 ? (ntiles + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
-    unsigned* counter = static_cast<unsigned*>(scratch);
-    double* partial = scratch_partials(scratch);
-    double* level = partial + chunks * kMergeChunkTiles * nbt;
-    hipLaunchKernelGGL(merge_kernel, dim3(unsigned(chunks)), dim3(kMergeThreads), 0, stream,
-                       partial, ntiles, chunks, nbt, level, counter, hist_out);
-    return hipGetLastError();
+    return size_t(n_sets) * size_t(p.tile_set_stride + 2 * p.level_set_stride) * sizeof(double);
+}
+
+hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, double* hist_out,
+                        hipStream_t stream)
+{
+    double* bufs[2] = {scratch + n_sets * p.tile_set_stride,
+                       scratch + n_sets * (p.tile_set_stride + p.level_set_stride)};
+    const double* in = scratch;
+    for (size_t l = 0; l < p.levels.size(); ++l) {
+        const MergeLevel& L = p.levels[l];
+        const dim3 grid{unsigned(L.total_chunks), unsigned(n_sets)};
+        const bool final_level = l + 1 == p.levels.size();
+        double* out = final_level ? hist_out : bufs[l % 2];
+        if (final_level)
+            hipLaunchKernelGGL(merge_level_kernel<true>, grid, dim3(kMergeThreads), 0, stream, L,
+                               in, out);
+        else
+            hipLaunchKernelGGL(merge_level_kernel<false>, grid, dim3(kMergeThreads), 0, stream, L,
+                               in, out);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        in = out;
+    }
+    return hipSuccess;
 }
 
 hipError_t occupancy(int mode, int nbins, int* blocks_per_cu)

@@ -1,6 +1,8 @@
 // Kernel launchers of libosc (defined in osc_kernels.hip).
 #pragma once
 
+#include <vector>
+
 #include "osc_internal.h"
 
 namespace osc {
@@ -16,18 +18,25 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const double* e_reco, const double* value, double* p_out,
                         double* partial, hipStream_t stream);
 
-// Bytes of scratch one histogram needs: merge counter, tile results,
-// chunk results.
-size_t merge_scratch_bytes(int64_t n, int nbt);
+// The levels of the histogram merge for n_samples samples of tiles[s]
+// tiles each (per parameter set), and the scratch strides they need.
+struct MergePlan {
+    int nbt = 0;
+    int n_samples = 0;
+    std::vector<MergeLevel> levels;
+    int64_t tile_set_stride = 0;   // elements of tile results per set
+    int64_t level_set_stride = 0;  // elements of each of the two level buffers per set
+};
 
-// Tile results of the scratch buffer (after the merge counter).
-inline double* scratch_partials(void* scratch)
-{
-    return reinterpret_cast<double*>(static_cast<char*>(scratch) + kMergeCounterBytes);
-}
+MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt);
 
-// Adds the tile results of every histogram entry into hist_out.
-hipError_t launch_merge(void* scratch, int64_t n, int nbt, double* hist_out, hipStream_t stream);
+// Scratch (bytes) for the tile results and the level buffers of n_sets sets.
+size_t merge_scratch_bytes(const MergePlan& p, int64_t n_sets);
+
+// Runs the merge levels on `stream`: tile results at the start of scratch,
+// histograms hist_out[set][sample][bin].
+hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, double* hist_out,
+                        hipStream_t stream);
 
 // Resident one-wave blocks per CU of the per-event kernel of `mode` for
 // histograms of nbins bins.

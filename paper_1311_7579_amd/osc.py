@@ -46,6 +46,31 @@ class osc_binning(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
 
 
+class osc_batch_config(ctypes.Structure):
+    _fields_ = [("sets_per_item", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+SCHEDULE_DYNAMIC, SCHEDULE_STATIC, SCHEDULE_ONE_PER_BLOCK = 0, 1, 2
+
+
+class osc_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("scratch_budget_bytes", ctypes.c_int64)]
+
+
+class osc_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in (
+        "submitted", "admitted", "completed", "failed", "rejected", "in_flight", "max_in_flight",
+        "queued", "max_queued", "budget_waits", "peak_scratch_bytes", "scratch_in_use_bytes")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class OscError(RuntimeError):
     def __init__(self, status, what=""):
         self.status = status
@@ -91,6 +116,37 @@ def load():
     L.osc_occupancy.restype = st
     L.osc_max_nbins.argtypes = [vp]
     L.osc_max_nbins.restype = i32
+    L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
+                                   ctypes.c_int, i32, ctypes.POINTER(vp)]
+    L.osc_batch_create.restype = st
+    L.osc_batch_destroy.argtypes = [vp]
+    L.osc_batch_destroy.restype = st
+    L.osc_batch_get_config.argtypes = [vp, ctypes.POINTER(osc_batch_config)]
+    L.osc_batch_get_config.restype = st
+    L.osc_batch_set_config.argtypes = [vp, ctypes.POINTER(osc_batch_config)]
+    L.osc_batch_set_config.restype = st
+    L.osc_batch_run.argtypes = [vp, ctypes.POINTER(osc_params), i32, vp, vp]
+    L.osc_batch_run.restype = st
+    L.osc_batch_tune.argtypes = [vp, ctypes.POINTER(osc_params), i32, ctypes.c_char_p,
+                                 ctypes.POINTER(ctypes.c_double), vp]
+    L.osc_batch_tune.restype = st
+    L.osc_server_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
+                                    ctypes.POINTER(osc_server_config), ctypes.POINTER(vp)]
+    L.osc_server_create.restype = st
+    L.osc_server_destroy.argtypes = [vp]
+    L.osc_server_destroy.restype = st
+    L.osc_server_submit.argtypes = [vp, ctypes.POINTER(osc_params), i32, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+    L.osc_server_submit.restype = st
+    for name in ("osc_server_poll", "osc_server_wait"):
+        fn = getattr(L, name)
+        fn.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double),
+                       ctypes.POINTER(ctypes.c_double)]
+        fn.restype = st
+    L.osc_server_get_stats.argtypes = [vp, ctypes.POINTER(osc_server_stats)]
+    L.osc_server_get_stats.restype = st
+    L.osc_server_request_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    L.osc_server_request_bytes.restype = st
     L.osc_status_string.argtypes = [ctypes.c_int]
     L.osc_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -247,3 +303,138 @@ class Context:
         _check(load().osc_fill_hist(self.handle, n, _ptr(value), _ptr(weight), _ptr(e_reco),
                                     ctypes.byref(b), _ptr(hist_out), _stream(stream)),
                "osc_fill_hist")
+
+
+class Batch:
+    """osc_batch: every parameter set x every sample in one persistent launch.
+
+    The DeviceSample tensors are kept referenced for the life of the batch
+    (the captured graph holds their addresses)."""
+
+    def __init__(self, ctx: Context, samples, nbins, lo, hi, precision=OSC_FP32_MIXED,
+                 max_sets=256):
+        self.ctx = ctx
+        self.samples = list(samples)
+        self.nbins = int(nbins)
+        self.max_sets = int(max_sets)
+        arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
+        b = osc_binning(self.nbins, float(lo), float(hi))
+        h = ctypes.c_void_p()
+        _check(load().osc_batch_create(ctx.handle, arr, len(self.samples), ctypes.byref(b),
+                                       int(precision), self.max_sets, ctypes.byref(h)),
+               "osc_batch_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().osc_batch_destroy(self.handle), "osc_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def config(self) -> osc_batch_config:
+        c = osc_batch_config()
+        _check(load().osc_batch_get_config(self.handle, ctypes.byref(c)), "osc_batch_get_config")
+        return c
+
+    @config.setter
+    def config(self, c):
+        if isinstance(c, dict):
+            cur = self.config
+            for k, v in c.items():
+                setattr(cur, k, int(v))
+            c = cur
+        _check(load().osc_batch_set_config(self.handle, ctypes.byref(c)), "osc_batch_set_config")
+
+    def run(self, sets, hist_out=None, stream=None):
+        """Histograms (n_sets, n_samples, nbins + 2) on the device."""
+        import torch
+        arr = params_array(sets)
+        if hist_out is None:
+            hist_out = torch.empty((len(arr), len(self.samples), self.nbins + 2),
+                                   dtype=torch.float64, device=self.samples[0].e_true.device)
+        _check(load().osc_batch_run(self.handle, arr, len(arr), _ptr(hist_out), _stream(stream)),
+               "osc_batch_run")
+        return hist_out
+
+    def tune(self, sets, cache_path=None, stream=None) -> float:
+        arr = params_array(sets)
+        ms = ctypes.c_double()
+        path = cache_path.encode() if cache_path else None
+        _check(load().osc_batch_tune(self.handle, arr, len(arr), path, ctypes.byref(ms),
+                                     _stream(stream)), "osc_batch_tune")
+        return ms.value
+
+
+class Server:
+    """osc_server: FIFO request loop with slot- and memory-bound admission.
+
+    Results come back as numpy arrays (nbins + 2 bins, host memory)."""
+
+    def __init__(self, ctx: Context, samples, nbins, lo, hi, slots=8, scratch_budget_bytes=1 << 30,
+                 queue_capacity=1 << 20):
+        self.ctx = ctx
+        self.samples = list(samples)
+        self.nbins = int(nbins)
+        arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
+        b = osc_binning(self.nbins, float(lo), float(hi))
+        cfg = osc_server_config(int(slots), int(queue_capacity), int(scratch_budget_bytes))
+        h = ctypes.c_void_p()
+        _check(load().osc_server_create(ctx.handle, arr, len(self.samples), ctypes.byref(b),
+                                        ctypes.byref(cfg), ctypes.byref(h)), "osc_server_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().osc_server_destroy(self.handle), "osc_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, params, sample, precision=OSC_FP64) -> int:
+        t = ctypes.c_uint64()
+        p = to_params(params)
+        _check(load().osc_server_submit(self.handle, ctypes.byref(p), int(sample), int(precision),
+                                        ctypes.byref(t)), "osc_server_submit")
+        return t.value
+
+    def _result(self, fn, ticket):
+        import numpy as np
+        h = np.empty(self.nbins + 2, dtype=np.float64)
+        lat, q = ctypes.c_double(), ctypes.c_double()
+        st = fn(self.handle, ctypes.c_uint64(ticket), ctypes.c_void_p(h.ctypes.data),
+                ctypes.byref(lat), ctypes.byref(q))
+        return st, h, lat.value, q.value
+
+    def poll(self, ticket):
+        """(hist, latency_s, queue_s) once done, else None."""
+        st, h, lat, q = self._result(load().osc_server_poll, ticket)
+        if st == OSC_ERR_NOT_READY:
+            return None
+        _check(st, "osc_server_poll")
+        return h, lat, q
+
+    def wait(self, ticket):
+        st, h, lat, q = self._result(load().osc_server_wait, ticket)
+        _check(st, "osc_server_wait")
+        return h, lat, q
+
+    def stats(self) -> dict:
+        s = osc_server_stats()
+        _check(load().osc_server_get_stats(self.handle, ctypes.byref(s)), "osc_server_get_stats")
+        return s.as_dict()
+
+    def request_bytes(self, sample) -> int:
+        b = ctypes.c_int64()
+        _check(load().osc_server_request_bytes(self.handle, int(sample), ctypes.byref(b)),
+               "osc_server_request_bytes")
+        return b.value

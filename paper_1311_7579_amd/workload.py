@@ -143,6 +143,69 @@ def make_random_physics_sets(n_sets, seed):
     return out
 
 
+def make_batched_samples(sizes=(100_000, 500_000, 2_000_000, 5_000_000),
+                         L_km=(295.0, 810.0, 1300.0, 2500.0), seeds=(41, 42, 43, 44),
+                         rho_range=(2.4, 3.0), rho_seed=40):
+    """Uneven samples of the batched form: one long-baseline sample per
+    (size, baseline, seed); densities drawn uniformly on rho_range from
+    their own PCG64 stream (one draw per sample, in order)."""
+    rng = np.random.Generator(np.random.PCG64(rho_seed))
+    rhos = rng.uniform(rho_range[0], rho_range[1], len(sizes))
+    return [make_sample(n, seed, L_km=L, rho_gcc=float(r))
+            for n, L, seed, r in zip(sizes, L_km, seeds, rhos)]
+
+
+SERVING_SIZES = tuple(int(round(v)) for v in np.geomspace(1e4, 2e7, 8))
+
+
+def make_serving_samples(sizes=SERVING_SIZES, seeds=tuple(range(51, 59)),
+                         baselines=(295.0, 810.0, 1300.0, 2500.0), rho_range=(2.4, 3.0),
+                         rho_seed=50):
+    """The resident samples of the serving form: log-spaced sizes, baselines
+    cycling through `baselines`, densities U(rho_range) from their own
+    PCG64 stream (one draw per sample, in order)."""
+    rng = np.random.Generator(np.random.PCG64(rho_seed))
+    rhos = rng.uniform(rho_range[0], rho_range[1], len(sizes))
+    return [make_sample(n, seed, L_km=baselines[k % len(baselines)], rho_gcc=float(rhos[k]))
+            for k, (n, seed) in enumerate(zip(sizes, seeds))]
+
+
+def make_proposal_stream(n, seed, n_samples, start=None, step=0.01, p_mixed=0.5):
+    """Metropolis-style proposals around Table 1: a random walk where each
+    proposal takes Gaussian steps of relative size `step` on the five
+    positive parameters (sin^2 clipped to [0, 1]) and an additive
+    step * 2 pi on delta_cp (wrapped to (-pi, pi]); every proposal becomes
+    the next state.  Each request also draws a sample index uniformly and a
+    precision tier (1 = FP32-mixed with probability p_mixed, else 0 = FP64).
+    Draw order per request: five relative steps, the phase step, the sample
+    index, the tier."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cur = dict(TABLE1 if start is None else start)
+    out = []
+    pos = ("sin2_th12", "sin2_th23", "sin2_th13", "dm2_32", "dm2_21")
+    for _ in range(n):
+        rel = rng.normal(0.0, step, 5)
+        dphi = rng.normal(0.0, step * 2 * math.pi)
+        sample = int(rng.integers(0, n_samples))
+        tier = int(rng.random() < p_mixed)
+        nxt = dict(cur)
+        for k, f in enumerate(pos):
+            nxt[f] = cur[f] * (1.0 + rel[k])
+        for f in ("sin2_th12", "sin2_th23", "sin2_th13"):
+            nxt[f] = min(max(nxt[f], 0.0), 1.0)
+        d = cur["delta_cp"] + dphi
+        nxt["delta_cp"] = math.remainder(d, 2 * math.pi) if abs(d) > math.pi else d
+        out.append((nxt, sample, tier))
+        cur = nxt
+    return out
+
+
+def poisson_arrivals(n, rate_hz, seed):
+    """Arrival times (s) of a Poisson process: cumulative exponential gaps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate_hz, n))
+
+
 # The evaluation workloads: per-event parity case, the full-size plain
 # case, the precision form, the batched form and the serving form.
 C1 = dict(name="plain-fp64-1e5", n=100_000, seed=1)

@@ -1,0 +1,127 @@
+"""GPU tests of the serving form (osc_server_*): results are bit-identical
+to osc_fill_pdf alone and in a concurrent mix, admission respects the slot
+count and the scratch budget, the queue refuses what it cannot take."""
+import numpy as np
+import pytest
+
+from paper_1311_7579_amd import workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def osc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1311_7579_amd import osc as _osc
+    _osc.load()
+    return _osc
+
+
+@pytest.fixture(scope="module")
+def ctx(osc):
+    c = osc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def resident(osc):
+    samples = workload.make_serving_samples(sizes=(10_000, 100_003, 1_000_000, 3_000_001),
+                                            seeds=(61, 62, 63, 64))
+    return samples, [osc.DeviceSample.from_host(s) for s in samples]
+
+
+def plain(osc, ctx, ds, params, tier):
+    ctx.osc_set_params([params])
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, None, precision=tier)
+    torch.cuda.synchronize()
+    return h.cpu().numpy()
+
+
+def test_server_alone_equals_mix_equals_plain(osc, ctx, resident):
+    samples, ds = resident
+    reqs = workload.make_proposal_stream(40, 71, len(ds))
+    server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=6, scratch_budget_bytes=256 << 20)
+    try:
+        alone = []
+        for p, s, tier in reqs:                      # one request at a time
+            alone.append(server.wait(server.submit(p, s, tier))[0])
+        tickets = [server.submit(p, s, tier) for p, s, tier in reqs]   # all at once
+        mix = [server.wait(t)[0] for t in tickets]
+        st = server.stats()
+    finally:
+        server.close()
+    for k, (p, s, tier) in enumerate(reqs):
+        np.testing.assert_array_equal(alone[k], mix[k], err_msg=f"request {k}")
+        np.testing.assert_array_equal(alone[k], plain(osc, ctx, ds[s], p, tier),
+                                      err_msg=f"request {k} vs plain")
+    assert st["completed"] == 80 and st["failed"] == 0
+    assert st["max_in_flight"] > 1          # the mix really ran concurrently
+
+
+def test_server_admission_by_budget(osc, ctx, resident):
+    samples, ds = resident
+    server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=8, scratch_budget_bytes=64 << 20)
+    try:
+        big = server.request_bytes(3)
+        server.close()
+        # room for exactly two of the largest requests
+        server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=8,
+                            scratch_budget_bytes=2 * ((big + 255) // 256 * 256))
+        reqs = [(workload.TABLE1, 3, k % 2) for k in range(12)]
+        tickets = [server.submit(p, s, t) for p, s, t in reqs]
+        res = [server.wait(t)[0] for t in tickets]
+        st = server.stats()
+    finally:
+        server.close()
+    assert st["max_in_flight"] <= 2
+    assert st["budget_waits"] >= 1
+    assert st["peak_scratch_bytes"] <= 2 * ((big + 255) // 256 * 256)
+    for k, (p, s, t) in enumerate(reqs):
+        np.testing.assert_array_equal(res[k], plain(osc, ctx, ds[s], p, t))
+
+
+def test_server_refusals(osc, ctx, resident):
+    samples, ds = resident
+    server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=1, scratch_budget_bytes=1 << 20,
+                        queue_capacity=2)
+    try:
+        with pytest.raises(osc.OscError):
+            server.submit(workload.TABLE1, 3, 0)        # larger than the whole budget
+        with pytest.raises(osc.OscError):
+            server.submit(workload.TABLE1, 9, 0)        # no such sample
+        with pytest.raises(osc.OscError):
+            server.submit(dict(workload.TABLE1, dm2_21=-1.0), 0, 0)
+        tickets, refused = [], 0
+        for _ in range(50):
+            try:
+                tickets.append(server.submit(workload.TABLE1, 0, 0))
+            except osc.OscError:
+                refused += 1
+        for t in tickets:
+            server.wait(t)
+        st = server.stats()
+        assert st["rejected"] == refused
+        assert st["max_queued"] <= 2
+    finally:
+        server.close()
+
+
+def test_server_poisson_stream(osc, ctx, resident):
+    from paper_1311_7579_amd import serving
+    samples, ds = resident
+    reqs = workload.make_proposal_stream(200, 72, len(ds))
+    arr = workload.poisson_arrivals(200, 2000.0, 73)
+    server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=8, scratch_budget_bytes=256 << 20)
+    try:
+        res, summ = serving.run_stream(server, reqs, arr, [s.n for s in samples])
+    finally:
+        server.close()
+    assert summ["stats"]["completed"] == 200
+    assert 0 < summ["p50_ms"] <= summ["p99_ms"]
+    for k in (0, 57, 199):
+        p, s, t = reqs[k]
+        np.testing.assert_array_equal(res[k], plain(osc, ctx, ds[s], p, t))
