@@ -81,14 +81,18 @@ typedef struct {
 } osc_sample;
 
 /* Regular binning of the reconstructed energy: nbins bins of width
- * wb = (hi - lo) / nbins (IEEE FP64).  An event falls into bin
- * floor((x - lo) / wb) (FP64 subtraction and division), into the underflow
- * entry when that quotient is negative, and into the overflow entry when it
- * is >= nbins or NaN.  Histogram layout: nbins bins, underflow, overflow.
- * 1 <= nbins <= osc_max_nbins(); lo < hi, both finite. */
+ * wb = (hi - lo) / nbins (IEEE FP64).  With x = e_reco * (1 + e_scale)
+ * (both operations in FP64, e_scale a relative energy-scale shift, 0 for
+ * none; Sec. 1.1.1 names this systematic and the event migration it
+ * causes), an event falls into bin floor((x - lo) / wb) (FP64 subtraction
+ * and division), into the underflow entry when that quotient is negative,
+ * and into the overflow entry when it is >= nbins or NaN.  Histogram
+ * layout: nbins bins, underflow, overflow.
+ * 1 <= nbins <= osc_max_nbins(); lo < hi, both finite; e_scale > -1. */
 typedef struct {
     int32_t nbins;
     double lo, hi;
+    double e_scale;
 } osc_binning;
 
 /* Create a context on HIP device `device`.  Returns OSC_ERR_DEVICE when no
@@ -154,6 +158,18 @@ osc_status osc_profile_enable(osc_ctx* ctx, int on);
  * Any output pointer may be NULL. */
 osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
                             double* merge_kernel_ms, int64_t* merge_kernel_launches);
+
+/* Sec. 2.2, Eq. (2): the binned likelihood of the fitter, read as a
+ * product over the regular bins of Poisson probabilities of observed counts
+ * d_b given the PDF mu_b:  -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)
+ * (a bin with mu_b = 0 adds 0 if d_b = 0, else +infinity; under/overflow
+ * entries are not used).  hist: device, n_hist histograms of nbins + 2
+ * entries (the layout of osc_fill_pdf / osc_batch_run); data: device,
+ * n_data rows of nbins counts, histogram k compared with row k % n_data
+ * (so batched histograms [set][sample] pair with per-sample data rows);
+ * nll_out: device, n_hist values.  The sum over bins has a fixed order. */
+osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, const double* data,
+                           int64_t n_data, int32_t nbins, double* nll_out, void* stream);
 
 /* ---- Batched form ---------------------------------------------------------
  * Every parameter set x every sample of a list in one persistent kernel

@@ -65,9 +65,13 @@ def lib():
         L.oracle_bin_index.argtypes = [d, d, d, i32]
         L.oracle_bin_index.restype = i32
         L.oracle_hist_contract.argtypes = [vp, vp, i64, i32, i32, i32, vp]
-        L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, i32, i32, vp, vp]
+        L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, d, i32, i32, vp, vp]
+        L.oracle_bin_index_scaled.argtypes = [d, d, d, d, i32]
+        L.oracle_bin_index_scaled.restype = i32
         L.oracle_fill_pdf.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_poisson_nll.argtypes = [vp, vp, i32]
+        L.oracle_poisson_nll.restype = d
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_set_num_threads.restype = None
         _lib = L
@@ -129,9 +133,11 @@ def bin_index(x, lo, hi, nbins) -> int:
     return lib().oracle_bin_index(float(x), float(lo), float(hi), int(nbins))
 
 
-def bin_indices(x, lo, hi, nbins) -> np.ndarray:
-    return np.array([bin_index(v, lo, hi, nbins) for v in np.asarray(x, dtype=np.float64)],
-                    dtype=np.int32)
+def bin_indices(x, lo, hi, nbins, e_scale=0.0) -> np.ndarray:
+    L = lib()
+    return np.array([L.oracle_bin_index_scaled(float(v), float(e_scale), float(lo), float(hi),
+                                               int(nbins))
+                     for v in np.asarray(x, dtype=np.float64)], dtype=np.int32)
 
 
 def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K) -> np.ndarray:
@@ -146,8 +152,16 @@ def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K) -> np.ndarray:
     return out
 
 
+def poisson_nll(mu, data) -> float:
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    d = np.ascontiguousarray(data, dtype=np.float64)
+    if m.shape != d.shape:
+        raise ValueError("mu and data differ in length")
+    return lib().oracle_poisson_nll(_ptr(m), _ptr(d), m.size)
+
+
 def fill_pdf(params, L_km, rho, Ye, e_true, flags, weight, e_reco, nbins, lo, hi,
-             W=CONTRACT_W, K=CONTRACT_K, want_p=True):
+             W=CONTRACT_W, K=CONTRACT_K, want_p=True, e_scale=0.0):
     e = np.ascontiguousarray(e_true, dtype=np.float64)
     f = np.ascontiguousarray(flags, dtype=np.uint8)
     w = np.ascontiguousarray(weight, dtype=np.float64)
@@ -159,5 +173,5 @@ def fill_pdf(params, L_km, rho, Ye, e_true, flags, weight, e_reco, nbins, lo, hi
     pp = to_params(params)
     lib().oracle_fill_pdf(ctypes.byref(pp), float(L_km), float(rho), float(Ye), e.size,
                           _ptr(e), _ptr(f), _ptr(w), _ptr(r), int(nbins), float(lo), float(hi),
-                          int(W), int(K), _ptr(hist), _ptr(p) if p is not None else ctypes.c_void_p(0))
+                          float(e_scale), int(W), int(K), _ptr(hist), _ptr(p) if p is not None else ctypes.c_void_p(0))
     return hist, p

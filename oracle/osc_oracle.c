@@ -251,6 +251,13 @@ int32_t oracle_bin_index(double x, double lo, double hi, int32_t nbins)
     return (int32_t)floor(q);
 }
 
+int32_t oracle_bin_index_scaled(double x, double e_scale, double lo, double hi, int32_t nbins)
+{
+    const double scale = 1.0 + e_scale;
+    const double xs = x * scale;
+    return oracle_bin_index(xs, lo, hi, nbins);
+}
+
 /* complete binary tree sum of v[0..npow2), entries at or beyond nreal
  * counting as +0.0; left subtree + right subtree at every node */
 static double tree_sum(const double* v, int64_t nreal, int64_t npow2)
@@ -299,10 +306,25 @@ void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
     free(tiles);
 }
 
+double oracle_poisson_nll(const double* mu, const double* data, int32_t nbins)
+{
+    double s = 0.0;
+    for (int32_t b = 0; b < nbins; ++b) {
+        const double m = mu[b], d = data[b];
+        double term;
+        if (m == 0.0)
+            term = d == 0.0 ? 0.0 : INFINITY;
+        else
+            term = m - d * log(m) + lgamma(d + 1.0);
+        s += term;
+    }
+    return 2.0 * s;
+}
+
 int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int64_t n, const double* e_true, const uint8_t* flags,
                     const double* weight, const double* e_reco,
-                    int32_t nbins, double lo, double hi, int32_t W, int32_t K,
+                    int32_t nbins, double lo, double hi, double e_scale, int32_t W, int32_t K,
                     double* hist_out, double* p_out)
 {
     double* prob = p_out ? p_out : (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
@@ -312,7 +334,7 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         c[i] = weight[i] * prob[i];
-        b[i] = oracle_bin_index(e_reco[i], lo, hi, nbins);
+        b[i] = oracle_bin_index_scaled(e_reco[i], e_scale, lo, hi, nbins);
     }
     oracle_hist_contract(c, b, n, nbins + 2, W, K, hist_out);
     free(b);

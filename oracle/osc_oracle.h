@@ -71,6 +71,11 @@ int oracle_prob_batch(const oracle_params* p, double L_km, double rho, double Ye
  * (underflow), q >= nbins or NaN -> nbins + 1 (overflow), else floor(q). */
 int32_t oracle_bin_index(double x, double lo, double hi, int32_t nbins);
 
+/* Bin index of a reconstructed energy under a relative energy-scale shift
+ * (the systematic of Sec. 1.1.1): the bin of x * (1 + e_scale), both FP64
+ * operations, by the rule above. */
+int32_t oracle_bin_index_scaled(double x, double e_scale, double lo, double hi, int32_t nbins);
+
 /* Deterministic histogram of contributions c[i] into bin[i] (values in
  * [0, nbt)) following the tile reduction contract with tile width W lanes
  * and K events per lane (both powers of two):
@@ -87,12 +92,19 @@ void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
 
 /* Plain reweight + binned PDF (Sec. 1.1.1): P per event, contribution
  * c = w * P (separately rounded), bin of e_reco, histogram by the tile
- * contract above.  hist_out has nbins + 2 entries; p_out may be NULL. */
+ * contract above, reconstructed energies scaled by (1 + e_scale) before
+ * binning.  hist_out has nbins + 2 entries; p_out may be NULL. */
 int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int64_t n, const double* e_true, const uint8_t* flags,
                     const double* weight, const double* e_reco,
-                    int32_t nbins, double lo, double hi, int32_t W, int32_t K,
+                    int32_t nbins, double lo, double hi, double e_scale, int32_t W, int32_t K,
                     double* hist_out, double* p_out);
+
+/* Sec. 2.2, Eq. (2), read as a product over the regular bins of Poisson
+ * probabilities of the observed counts d_b given the expectations mu_b:
+ * -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)  (ln d! = lgamma(d + 1)).
+ * A bin with mu_b = 0 adds 0 when d_b = 0 and +infinity otherwise. */
+double oracle_poisson_nll(const double* mu, const double* data, int32_t nbins);
 
 /* OpenMP thread count the batch functions use, and a setter (n > 0). */
 int oracle_num_threads(void);

@@ -254,7 +254,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
 // Such lanes are flagged and redone with the correctly rounded division.
 __device__ __forceinline__ double bin_floor_fast(double x, const BinConsts& bc, bool& edge)
 {
-    const double d = x - bc.lo;
+#pragma clang fp contract(off)
+    const double d = x * bc.scale - bc.lo;   // scaled energy, then the offset: two roundings
     const double q = d * bc.inv_wb;
     const double k = __builtin_floor(q);
     const double fr = q - k;
@@ -264,7 +265,8 @@ __device__ __forceinline__ double bin_floor_fast(double x, const BinConsts& bc, 
 
 __device__ __forceinline__ double bin_floor_exact(double x, const BinConsts& bc)
 {
-    return __builtin_floor((x - bc.lo) / bc.wb);
+#pragma clang fp contract(off)
+    return __builtin_floor((x * bc.scale - bc.lo) / bc.wb);
 }
 
 __device__ __forceinline__ int bin_index(double k, const BinConsts& bc)

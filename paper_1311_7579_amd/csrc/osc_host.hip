@@ -233,6 +233,7 @@ bool osc::host::binning_ok(const osc_ctx* ctx, const osc_binning* b)
     if (!b || b->nbins < 1 || b->nbins > ctx->max_nbins) return false;
     if (!is_finite(b->lo) || !is_finite(b->hi) || !(b->lo < b->hi)) return false;
     const double wb = (b->hi - b->lo) / double(b->nbins);
+    if (!is_finite(b->e_scale) || !(b->e_scale > -1.0)) return false;
     return is_finite(wb) && wb > 0.0;
 }
 
@@ -244,7 +245,7 @@ osc::PathConsts osc::host::path_consts(const osc_sample* s)
 osc::BinConsts osc::host::bin_consts(const osc_binning* b)
 {
     const double wb = (b->hi - b->lo) / double(b->nbins);
-    return osc::BinConsts{b->lo, wb, 1.0 / wb, b->nbins};
+    return osc::BinConsts{b->lo, wb, 1.0 / wb, 1.0 + b->e_scale, b->nbins};
 }
 
 int osc::host::ctx_device(const osc_ctx* ctx) { return ctx->device; }
@@ -386,7 +387,7 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, dou
     std::lock_guard<std::mutex> lock(ctx->mu);
     if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
-    const osc::BinConsts bc{0.0, 1.0, 1.0, 1};
+    const osc::BinConsts bc{0.0, 1.0, 1.0, 1.0, 1};
     const hipStream_t hs = static_cast<hipStream_t>(stream);
     ProfRec* pr = prof_begin(ctx, hs);
     const hipError_t e = osc::launch_tiles(0, true, false, ctx->consts[size_t(set)],
@@ -474,6 +475,18 @@ osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* even
     if (merge_kernel_ms) *merge_kernel_ms = merge_ms;
     if (merge_kernel_launches) *merge_kernel_launches = merges;
     return st;
+}
+
+osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, const double* data,
+                           int64_t n_data, int32_t nbins, double* nll_out, void* stream)
+{
+    if (!ctx || n_hist < 0 || n_data < 1 || nbins < 1 || nbins > ctx->max_nbins)
+        return OSC_ERR_INVALID_ARG;
+    if (n_hist > 0 && (!hist || !data || !nll_out)) return OSC_ERR_INVALID_ARG;
+    if (n_hist > int64_t(1) << 31) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    return device_status(osc::launch_poisson_nll(hist, n_hist, data, n_data, nbins, nll_out,
+                                                 static_cast<hipStream_t>(stream)));
 }
 
 void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events)

@@ -75,6 +75,7 @@ struct BinConsts {
     double lo;
     double wb;      // (hi - lo) / nbins, computed on the host in FP64
     double inv_wb;  // 1 / wb rounded to FP64 (fast path of the bin index)
+    double scale;   // 1 + e_scale rounded to FP64; the bin is taken for x * scale
     int32_t nb;     // regular bins; entries nb and nb + 1 are under/overflow
 };
 

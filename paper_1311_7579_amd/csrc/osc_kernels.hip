@@ -70,7 +70,40 @@ __global__ __launch_bounds__(kMergeThreads) void merge_level_kernel(MergeLevel L
     merge_level_block<FINAL>(L, in, out);
 }
 
+// Eq. (2) as a product of Poisson probabilities over the regular bins:
+// -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + lgamma(d_b + 1)).  One wave per
+// histogram; lane l adds bins l, l + 64, ... in ascending order, then the
+// lanes meet in the wave's butterfly tree (a fixed order).
+__global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restrict__ hist,
+                                                         int64_t n_data,
+                                                         const double* __restrict__ data,
+                                                         int nbins, double* __restrict__ out)
+{
+    const int64_t k = blockIdx.x;
+    const int lane = threadIdx.x;
+    const double* mu = hist + k * (nbins + 2);
+    const double* d = data + (k % n_data) * nbins;
+    double acc = 0.0;
+    for (int b = lane; b < nbins; b += 64) {
+        const double m = mu[b], x = d[b];
+        const double term = m == 0.0 ? (x == 0.0 ? 0.0 : __builtin_inf())
+                                     : m - x * log(m) + lgamma(x + 1.0);
+        acc = acc + term;
+    }
+    acc = wave_tree(acc);
+    if (lane == 0) out[k] = 2.0 * acc;
+}
+
 }  // namespace
+
+hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, const double* data,
+                              int64_t n_data, int nbins, double* out, hipStream_t stream)
+{
+    if (n_hist == 0) return hipSuccess;
+    hipLaunchKernelGGL(poisson_nll_kernel, dim3(unsigned(n_hist)), dim3(64), 0, stream, hist,
+                       n_data, data, nbins, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const PathConsts& pc, const BinConsts& bc, int64_t n,

@@ -38,6 +38,12 @@ size_t merge_scratch_bytes(const MergePlan& p, int64_t n_sets);
 hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, double* hist_out,
                         hipStream_t stream);
 
+// -2 ln L (Eq. 2, Poisson per regular bin) of n_hist histograms
+// (nbins + 2 entries each) against data rows (nbins entries; histogram k
+// uses row k % n_data).
+hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, const double* data,
+                              int64_t n_data, int nbins, double* out, hipStream_t stream);
+
 // Resident one-wave blocks per CU of the per-event kernel of `mode` for
 // histograms of nbins bins.
 hipError_t occupancy(int mode, int nbins, int* blocks_per_cu);

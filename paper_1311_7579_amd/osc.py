@@ -43,7 +43,8 @@ class osc_sample(ctypes.Structure):
 
 
 class osc_binning(ctypes.Structure):
-    _fields_ = [("nbins", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+    _fields_ = [("nbins", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("e_scale", ctypes.c_double)]
 
 
 class osc_batch_config(ctypes.Structure):
@@ -116,6 +117,8 @@ def load():
     L.osc_occupancy.restype = st
     L.osc_max_nbins.argtypes = [vp]
     L.osc_max_nbins.restype = i32
+    L.osc_poisson_nll.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+    L.osc_poisson_nll.restype = st
     L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                    ctypes.c_int, i32, ctypes.POINTER(vp)]
     L.osc_batch_create.restype = st
@@ -278,9 +281,9 @@ class Context:
                                    _stream(stream)), "osc_reweight")
 
     def osc_fill_pdf(self, sample: DeviceSample, set_index, nbins, lo, hi, hist_out,
-                     p_out=None, precision=OSC_FP64, stream=None):
+                     p_out=None, precision=OSC_FP64, stream=None, e_scale=0.0):
         cs = sample.c_struct()
-        b = osc_binning(int(nbins), float(lo), float(hi))
+        b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
         _check(load().osc_fill_pdf(self.handle, ctypes.byref(cs), int(set_index), ctypes.byref(b),
                                    int(precision), _ptr(hist_out), _ptr(p_out), _stream(stream)),
                "osc_fill_pdf")
@@ -297,8 +300,18 @@ class Context:
                                        ctypes.byref(c), ctypes.byref(d)), "osc_profile_read")
         return a.value, b.value, c.value, d.value
 
-    def osc_fill_hist(self, value, weight, e_reco, nbins, lo, hi, hist_out, stream=None):
-        b = osc_binning(int(nbins), float(lo), float(hi))
+    def osc_poisson_nll(self, hist, data, nll_out, stream=None):
+        """-2 ln L of every histogram in `hist` (..., nbins + 2) against the
+        rows of `data` (n_data, nbins); histogram k uses row k % n_data."""
+        nbins = int(data.shape[-1])
+        n_hist = int(hist.numel() // (nbins + 2))
+        n_data = int(data.numel() // nbins)
+        _check(load().osc_poisson_nll(self.handle, _ptr(hist), n_hist, _ptr(data), n_data, nbins,
+                                      _ptr(nll_out), _stream(stream)), "osc_poisson_nll")
+
+    def osc_fill_hist(self, value, weight, e_reco, nbins, lo, hi, hist_out, stream=None,
+                      e_scale=0.0):
+        b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
         n = int(value.numel())
         _check(load().osc_fill_hist(self.handle, n, _ptr(value), _ptr(weight), _ptr(e_reco),
                                     ctypes.byref(b), _ptr(hist_out), _stream(stream)),
@@ -312,13 +325,13 @@ class Batch:
     (the captured graph holds their addresses)."""
 
     def __init__(self, ctx: Context, samples, nbins, lo, hi, precision=OSC_FP32_MIXED,
-                 max_sets=256):
+                 max_sets=256, e_scale=0.0):
         self.ctx = ctx
         self.samples = list(samples)
         self.nbins = int(nbins)
         self.max_sets = int(max_sets)
         arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
-        b = osc_binning(self.nbins, float(lo), float(hi))
+        b = osc_binning(self.nbins, float(lo), float(hi), float(e_scale))
         h = ctypes.c_void_p()
         _check(load().osc_batch_create(ctx.handle, arr, len(self.samples), ctypes.byref(b),
                                        int(precision), self.max_sets, ctypes.byref(h)),
@@ -377,12 +390,12 @@ class Server:
     Results come back as numpy arrays (nbins + 2 bins, host memory)."""
 
     def __init__(self, ctx: Context, samples, nbins, lo, hi, slots=8, scratch_budget_bytes=1 << 30,
-                 queue_capacity=1 << 20):
+                 queue_capacity=1 << 20, e_scale=0.0):
         self.ctx = ctx
         self.samples = list(samples)
         self.nbins = int(nbins)
         arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
-        b = osc_binning(self.nbins, float(lo), float(hi))
+        b = osc_binning(self.nbins, float(lo), float(hi), float(e_scale))
         cfg = osc_server_config(int(slots), int(queue_capacity), int(scratch_budget_bytes))
         h = ctypes.c_void_p()
         _check(load().osc_server_create(ctx.handle, arr, len(self.samples), ctypes.byref(b),

@@ -33,7 +33,8 @@ def test_header_declares_the_entry_points():
     for want in ("osc_create", "osc_destroy", "osc_set_params", "osc_reweight", "osc_fill_pdf",
                  "osc_fill_hist", "osc_validate_params", "osc_reduction_layout",
                  "osc_max_nbins", "osc_status_string", "osc_occupancy", "osc_profile_enable",
-                 "osc_profile_read"):
+                 "osc_profile_read", "osc_poisson_nll", "osc_batch_create", "osc_batch_run",
+                 "osc_batch_tune", "osc_server_create", "osc_server_submit", "osc_server_wait"):
         assert want in names
 
 

@@ -375,3 +375,64 @@ def test_mixed_tier_all_channels(osc, ctx):
                 assert np.abs(host(pm) - po).max() <= MIXED_TOL, (L, rho, k)
     finally:
         ctx.osc_set_params([workload.TABLE1])
+
+
+# --------------------------------------------------------------- Eq. (2)
+def test_poisson_nll_against_oracle(osc, ctx):
+    rng = np.random.default_rng(31)
+    n_hist, n_data, nb = 12, 4, 50
+    mu = rng.uniform(0.0, 400.0, (n_hist, nb + 2))
+    mu[0, 3] = 0.0                                        # empty bin with empty data
+    data = rng.poisson(rng.uniform(1.0, 300.0, (n_data, nb))).astype(float)
+    data[0, 3] = 0.0
+    out = torch.empty(n_hist, dtype=torch.float64, device="cuda")
+    ctx.osc_poisson_nll(dev(mu), dev(data), out)
+    got = host(out)
+    for k in range(n_hist):
+        want = oracle.poisson_nll(mu[k, :nb], data[k % n_data])
+        assert got[k] == pytest.approx(want, rel=1e-12), k
+
+
+def test_poisson_nll_on_fitter_loop(osc, ctx):
+    """The fitter's step: PDF at a proposal, -2 ln L against fake data drawn
+    at Table 1; the likelihood is smallest near the generating point."""
+    s = workload.make_sample(400_000, 3)
+    ds = osc.DeviceSample.from_host(s)
+    sets = [workload.TABLE1, dict(workload.TABLE1, dm2_32=2.2e-3), dict(workload.TABLE1, sin2_th23=0.4)]
+    ctx.osc_set_params(sets)
+    try:
+        h = torch.empty((3, 52), dtype=torch.float64, device="cuda")
+        for k in range(3):
+            ctx.osc_fill_pdf(ds, k, 50, 0.0, 3.0, h[k])
+        data = np.random.default_rng(5).poisson(host(h)[0, :50]).astype(float)
+        out = torch.empty(3, dtype=torch.float64, device="cuda")
+        ctx.osc_poisson_nll(h, dev(data[None, :]), out)
+        got = host(out)
+        for k in range(3):
+            assert got[k] == pytest.approx(oracle.poisson_nll(host(h)[k, :50], data), rel=1e-12)
+        assert got[0] < got[1] and got[0] < got[2]
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
+
+
+# --------------------------------------------------------------- energy scale
+@pytest.mark.parametrize("e_scale", [0.0, 0.013, -0.021])
+def test_energy_scale_systematic(osc, ctx, e_scale):
+    """Event migration under a reco-energy scale shift: bins exact, histogram
+    bit-exact to the contract, P independent of the shift."""
+    s = workload.make_sample(300_007, 44)
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, p, e_scale=e_scale)
+    P = host(p)
+    bins = oracle.bin_indices(s.e_reco, 0.0, 3.0, 50, e_scale=e_scale)
+    np.testing.assert_array_equal(host(h), oracle.hist_contract(s.weight * P, bins, 52))
+    hist_o, P_o = oracle.fill_pdf(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                  s.weight, s.e_reco, 50, 0.0, 3.0, e_scale=e_scale)
+    assert np.abs(P - P_o).max() <= P_TOL
+    tol = hist_tolerance(s.weight, s.weight * P_o, bins, 52, s.n)
+    assert (np.abs(host(h) - hist_o) <= tol).all()
+    one = torch.ones(s.n, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(one, one, ds.e_reco, 50, 0.0, 3.0, h, e_scale=e_scale)
+    np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=52).astype(float))

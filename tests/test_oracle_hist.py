@@ -147,3 +147,45 @@ def test_vectorised_bin_rule_matches_oracle():
     np.testing.assert_array_equal(bins_np(x, 0.0, 3.0, 50), oracle.bin_indices(x, 0.0, 3.0, 50))
     x2 = np.random.default_rng(1).uniform(0.0, 10.0, 5_000)
     np.testing.assert_array_equal(bins_np(x2, 0.5, 9.5, 37), oracle.bin_indices(x2, 0.5, 9.5, 37))
+
+
+# ---------------------------------------------------------------- Eq. (2)
+def test_poisson_nll_matches_library_logpmf():
+    import scipy.stats
+    rng = np.random.default_rng(12)
+    mu = rng.uniform(0.1, 300.0, 50)
+    d = rng.poisson(mu).astype(float)
+    want = -2.0 * scipy.stats.poisson.logpmf(d, mu).sum()
+    assert oracle.poisson_nll(mu, d) == pytest.approx(want, rel=1e-13)
+
+
+def test_poisson_nll_empty_bins_and_best_normalisation():
+    assert oracle.poisson_nll([0.0, 2.0], [0.0, 2.0]) == pytest.approx(
+        2 * (2.0 - 2.0 * math.log(2.0) + math.log(2.0)), rel=1e-15)
+    assert math.isinf(oracle.poisson_nll([0.0, 1.0], [3.0, 1.0]))
+    # for mu = a * m the minimum over a sits at a = sum(d) / sum(m)
+    rng = np.random.default_rng(13)
+    m = rng.uniform(1.0, 50.0, 40)
+    d = rng.poisson(1.7 * m).astype(float)
+    a0 = d.sum() / m.sum()
+    f = lambda a: oracle.poisson_nll(a * m, d)
+    assert f(a0) < f(a0 * 1.001) and f(a0) < f(a0 * 0.999)
+
+
+# ---------------------------------------------------------------- energy scale
+def test_energy_scale_binning():
+    rng = np.random.default_rng(21)
+    x = rng.uniform(0.0, 3.0, 3000)
+    b0 = oracle.bin_indices(x, 0.0, 3.0, 50)
+    np.testing.assert_array_equal(oracle.bin_indices(x, 0.0, 3.0, 50, e_scale=0.0), b0)
+    # the definition: bin of fl(x * fl(1 + s)) by the unscaled rule
+    for s in (0.02, -0.05, 1e-9):
+        xs = x * (1.0 + s)
+        np.testing.assert_array_equal(oracle.bin_indices(x, 0.0, 3.0, 50, e_scale=s),
+                                      oracle.bin_indices(xs, 0.0, 3.0, 50))
+    # a positive shift only moves events up (migration), never down
+    up = oracle.bin_indices(x, 0.0, 3.0, 50, e_scale=0.03)
+    assert (up >= b0).all() and (up > b0).any()
+    # the boundary: 1.5 GeV sits on an edge; a 1e-12 shift moves it one bin down
+    assert oracle.bin_index(1.5, 0.0, 3.0, 50) == 25
+    assert oracle.bin_indices([1.5], 0.0, 3.0, 50, e_scale=-1e-12)[0] == 24
