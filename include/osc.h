@@ -130,9 +130,11 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
  * The histogram is bit-reproducible: it is the sum of the c values in a
  * fixed order that depends only on n and the event order, never on the
  * launch shape (see osc_reduction_layout): tiles of W*K consecutive events;
- * lane l of tile t sums events t*W*K + m*W + l for m = 0..K-1 in ascending
- * m starting from +0.0; per bin, the W lane sums of a tile meet in the
- * complete binary tree over lane index; the tile results meet in the
+ * lane l of tile t takes events t*W*K + m*W + l (m = 0..K-1) and adds them
+ * into accumulator l mod A of their bin; each accumulator starts from +0.0
+ * and receives its additions in ascending m and, within one m, in
+ * ascending l; per bin, the A accumulators of a tile meet in the complete
+ * binary tree over accumulator index; the tile results meet in the
  * complete binary tree over tile index, padded with +0.0 to a power of two. */
 osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         const osc_binning* binning, osc_precision precision,
@@ -191,7 +193,7 @@ typedef struct {
 /* Prepare a batched evaluation over n_samples (1..16) resident samples
  * (device arrays as in osc_sample; they must stay valid and unchanged for
  * the life of the batch), one binning and one precision, for up to max_sets
- * parameter sets per run.  Allocates the device scratch (tile results of
+ * (1..65535) parameter sets per run.  Allocates the device scratch (tile results of
  * max_sets sets) and chooses a default configuration. */
 osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_samples,
                             const osc_binning* binning, osc_precision precision, int32_t max_sets,
@@ -278,9 +280,9 @@ osc_status osc_server_get_stats(osc_server* server, osc_server_stats* out);
 /* Device scratch (bytes) one request on `sample` takes from the budget. */
 osc_status osc_server_request_bytes(const osc_server* server, int32_t sample, int64_t* bytes);
 
-/* Constants of the reduction contract: W lanes per tile and K events per
- * lane.  Either pointer may be NULL. */
-void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events);
+/* Constants of the reduction contract: W lanes per tile, K events per lane
+ * and A accumulators per bin of a tile.  Any pointer may be NULL. */
+void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events, int32_t* accumulators);
 
 /* Largest nbins osc_fill_pdf accepts on this context's device (the
  * per-lane histograms live in LDS). */

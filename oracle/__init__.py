@@ -18,9 +18,11 @@ from .build import LIB as _LIB_PATH
 
 _FIELDS = ("sin2_th12", "sin2_th23", "sin2_th13", "dm2_32", "dm2_21", "delta_cp")
 
-# tile reduction contract of the binned PDF: W lanes x K events per lane
+# tile reduction contract of the binned PDF: W lanes x K events per lane,
+# A accumulators per bin (lane l adds into accumulator l mod A)
 CONTRACT_W = 64
 CONTRACT_K = 16
+CONTRACT_A = 8
 
 
 class OracleParams(ctypes.Structure):
@@ -64,8 +66,9 @@ def lib():
         L.oracle_prob_batch.restype = ctypes.c_int
         L.oracle_bin_index.argtypes = [d, d, d, i32]
         L.oracle_bin_index.restype = i32
-        L.oracle_hist_contract.argtypes = [vp, vp, i64, i32, i32, i32, vp]
-        L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, d, i32, i32, vp, vp]
+        L.oracle_hist_contract.argtypes = [vp, vp, i64, i32, i32, i32, i32, vp]
+        L.oracle_fill_pdf.argtypes = [P, d, d, d, i64, vp, vp, vp, vp, i32, d, d, d, i32, i32, i32, vp,
+                                      vp]
         L.oracle_bin_index_scaled.argtypes = [d, d, d, d, i32]
         L.oracle_bin_index_scaled.restype = i32
         L.oracle_fill_pdf.restype = ctypes.c_int
@@ -140,15 +143,18 @@ def bin_indices(x, lo, hi, nbins, e_scale=0.0) -> np.ndarray:
                      for v in np.asarray(x, dtype=np.float64)], dtype=np.int32)
 
 
-def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K) -> np.ndarray:
+def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K, A=CONTRACT_A) -> np.ndarray:
     c = np.ascontiguousarray(c, dtype=np.float64)
     b = np.ascontiguousarray(bins, dtype=np.int32)
     if c.shape != b.shape:
         raise ValueError("c and bins differ in length")
     if b.size and (b.min() < 0 or b.max() >= nbt):
         raise ValueError("bin index out of range")
+    if W % A or A & (A - 1) or W & (W - 1) or K & (K - 1):
+        raise ValueError("W, K, A must be powers of two with A dividing W")
     out = np.zeros(int(nbt), dtype=np.float64)
-    lib().oracle_hist_contract(_ptr(c), _ptr(b), c.size, int(nbt), int(W), int(K), _ptr(out))
+    lib().oracle_hist_contract(_ptr(c), _ptr(b), c.size, int(nbt), int(W), int(K), int(A),
+                               _ptr(out))
     return out
 
 
@@ -161,7 +167,7 @@ def poisson_nll(mu, data) -> float:
 
 
 def fill_pdf(params, L_km, rho, Ye, e_true, flags, weight, e_reco, nbins, lo, hi,
-             W=CONTRACT_W, K=CONTRACT_K, want_p=True, e_scale=0.0):
+             W=CONTRACT_W, K=CONTRACT_K, A=CONTRACT_A, want_p=True, e_scale=0.0):
     e = np.ascontiguousarray(e_true, dtype=np.float64)
     f = np.ascontiguousarray(flags, dtype=np.uint8)
     w = np.ascontiguousarray(weight, dtype=np.float64)
@@ -173,5 +179,5 @@ def fill_pdf(params, L_km, rho, Ye, e_true, flags, weight, e_reco, nbins, lo, hi
     pp = to_params(params)
     lib().oracle_fill_pdf(ctypes.byref(pp), float(L_km), float(rho), float(Ye), e.size,
                           _ptr(e), _ptr(f), _ptr(w), _ptr(r), int(nbins), float(lo), float(hi),
-                          float(e_scale), int(W), int(K), _ptr(hist), _ptr(p) if p is not None else ctypes.c_void_p(0))
+                          float(e_scale), int(W), int(K), int(A), _ptr(hist), _ptr(p) if p is not None else ctypes.c_void_p(0))
     return hist, p

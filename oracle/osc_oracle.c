@@ -272,7 +272,7 @@ static double tree_sum(const double* v, int64_t nreal, int64_t npow2)
 }
 
 void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
-                          int32_t nbt, int32_t W, int32_t K, double* out)
+                          int32_t nbt, int32_t W, int32_t K, int32_t A, double* out)
 {
     const int64_t T = (int64_t)W * K;
     const int64_t ntiles = (n + T - 1) / T;
@@ -281,28 +281,30 @@ void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
 
     /* per-bin tile results, bin-major */
     double* tiles = (double*)calloc((size_t)(ntiles > 0 ? ntiles : 1) * nbt, sizeof(double));
-    double* lanes = (double*)malloc((size_t)W * nbt * sizeof(double));
-    double* col = (double*)malloc((size_t)W * sizeof(double));
+    double* acc = (double*)malloc((size_t)A * nbt * sizeof(double));
+    double* col = (double*)malloc((size_t)A * sizeof(double));
 
     for (int64_t t = 0; t < ntiles; ++t) {
-        /* every lane starts from +0.0 in every bin */
-        for (int64_t q = 0; q < (int64_t)W * nbt; ++q) lanes[q] = 0.0;
-        for (int32_t l = 0; l < W; ++l)
-            for (int32_t m = 0; m < K; ++m) {
+        /* every accumulator starts from +0.0 in every bin */
+        for (int64_t q = 0; q < (int64_t)A * nbt; ++q) acc[q] = 0.0;
+        /* event slot m after event slot m; within a slot, ascending lane,
+         * lane l adding into accumulator l mod A */
+        for (int32_t m = 0; m < K; ++m)
+            for (int32_t l = 0; l < W; ++l) {
                 const int64_t i = t * T + (int64_t)m * W + l;
                 if (i >= n) continue;
-                lanes[(int64_t)bin[i] * W + l] += c[i];
+                acc[(int64_t)bin[i] * A + l % A] += c[i];
             }
         for (int32_t b = 0; b < nbt; ++b) {
-            for (int32_t l = 0; l < W; ++l) col[l] = lanes[(int64_t)b * W + l];
-            tiles[(int64_t)b * ntiles + t] = tree_sum(col, W, W);
+            for (int32_t a = 0; a < A; ++a) col[a] = acc[(int64_t)b * A + a];
+            tiles[(int64_t)b * ntiles + t] = tree_sum(col, A, A);
         }
     }
     for (int32_t b = 0; b < nbt; ++b)
         out[b] = ntiles > 0 ? tree_sum(tiles + (int64_t)b * ntiles, ntiles, p2) : 0.0;
 
     free(col);
-    free(lanes);
+    free(acc);
     free(tiles);
 }
 
@@ -325,7 +327,7 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int64_t n, const double* e_true, const uint8_t* flags,
                     const double* weight, const double* e_reco,
                     int32_t nbins, double lo, double hi, double e_scale, int32_t W, int32_t K,
-                    double* hist_out, double* p_out)
+                    int32_t A, double* hist_out, double* p_out)
 {
     double* prob = p_out ? p_out : (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     double* c = (double*)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
@@ -336,7 +338,7 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
         c[i] = weight[i] * prob[i];
         b[i] = oracle_bin_index_scaled(e_reco[i], e_scale, lo, hi, nbins);
     }
-    oracle_hist_contract(c, b, n, nbins + 2, W, K, hist_out);
+    oracle_hist_contract(c, b, n, nbins + 2, W, K, A, hist_out);
     free(b);
     free(c);
     if (!p_out) free(prob);

@@ -77,18 +77,20 @@ int32_t oracle_bin_index(double x, double lo, double hi, int32_t nbins);
 int32_t oracle_bin_index_scaled(double x, double e_scale, double lo, double hi, int32_t nbins);
 
 /* Deterministic histogram of contributions c[i] into bin[i] (values in
- * [0, nbt)) following the tile reduction contract with tile width W lanes
- * and K events per lane (both powers of two):
+ * [0, nbt)) following the tile reduction contract with tile width W lanes,
+ * K events per lane and A accumulators per bin (powers of two, A divides W):
  *   tile t holds events t*W*K .. t*W*K + W*K - 1; lane l of the tile takes
- *   events t*W*K + m*W + l for m = 0..K-1 and sums them in ascending m,
- *   starting from +0.0, into a private per-bin accumulator;
- *   for each bin, the W lane sums of a tile are added by the complete
- *   binary tree over lane index (adjacent pairs first);
+ *   events t*W*K + m*W + l for m = 0..K-1;
+ *   lane l adds into accumulator l mod A of the event's bin; every
+ *   accumulator starts from +0.0 and receives its additions in ascending
+ *   m and, within one m, in ascending l;
+ *   for each bin, the A accumulators of a tile are added by the complete
+ *   binary tree over accumulator index (adjacent pairs first);
  *   for each bin, the tile results are added by the complete binary tree
  *   over tile index, padded with +0.0 to a power of two.
  * out has nbt entries. */
 void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
-                          int32_t nbt, int32_t W, int32_t K, double* out);
+                          int32_t nbt, int32_t W, int32_t K, int32_t A, double* out);
 
 /* Plain reweight + binned PDF (Sec. 1.1.1): P per event, contribution
  * c = w * P (separately rounded), bin of e_reco, histogram by the tile
@@ -98,7 +100,7 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int64_t n, const double* e_true, const uint8_t* flags,
                     const double* weight, const double* e_reco,
                     int32_t nbins, double lo, double hi, double e_scale, int32_t W, int32_t K,
-                    double* hist_out, double* p_out);
+                    int32_t A, double* hist_out, double* p_out);
 
 /* Sec. 2.2, Eq. (2), read as a product over the regular bins of Poisson
  * probabilities of the observed counts d_b given the expectations mu_b:

@@ -68,14 +68,15 @@ __global__ void reset_queue(unsigned* queue)
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(kTileLanes) void batch_kernel(BatchArgs a,
+__global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kBatchWavesPerSimd)))
+void batch_kernel(BatchArgs a,
                                                            const BatchSampleDev* __restrict__ samples,
                                                            const SetConsts* __restrict__ sets,
                                                            double* __restrict__ partial,
                                                            unsigned* __restrict__ queue)
 {
     extern __shared__ double hist[];
-    __shared__ Chan tab[9];
+    __shared__ Chan tab[kChannels];
     const int lane = threadIdx.x;
     const int nbt = a.nbt;
 
@@ -96,12 +97,7 @@ __global__ __launch_bounds__(kTileLanes) void batch_kernel(BatchArgs a,
         for (int set = int(g) * a.sets_per_item; set < set_end; ++set) {
             const SetConsts& sc = sets[set];
             __syncthreads();   // the previous set's table and histogram are read
-            if (lane < 54) {
-                const int e = lane / 6, f = lane - 6 * (lane / 6);
-                const int b = e / 3, al = e - 3 * (e / 3);
-                reinterpret_cast<double*>(tab)[lane] =
-                    reinterpret_cast<const double*>(&sc.ch[(b << 2) | al])[f];
-            }
+            load_tab(sc, tab, lane);
             hist_zero(hist, lane, nbt);
             __syncthreads();
             if (full)
@@ -185,7 +181,7 @@ osc::BatchArgs batch_args(const osc_batch* b, int n_sets, const osc_batch_config
 hipError_t enqueue(osc_batch* b, int n_sets, const osc_batch_config& c, hipStream_t stream)
 {
     const osc::BatchArgs a = batch_args(b, n_sets, c);
-    const size_t lds = size_t(a.nbt) * osc::kTileLanes * sizeof(double);
+    const size_t lds = size_t(a.nbt) * osc::kHistLanes * sizeof(double);
     int64_t grid = a.n_items;
     if (c.schedule != osc::kOnePerBlock) {
         const int wpc = c.waves_per_cu > 0 ? c.waves_per_cu : b->occupancy;
@@ -317,7 +313,8 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
 {
     if (!out) return OSC_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!ctx || !samples || n_samples < 1 || n_samples > osc::kMaxBatchSamples || max_sets < 1)
+    if (!ctx || !samples || n_samples < 1 || n_samples > osc::kMaxBatchSamples || max_sets < 1 ||
+        max_sets > osc::kMaxBatchSets)
         return OSC_ERR_INVALID_ARG;
     if (precision != OSC_FP64 && precision != OSC_FP32_MIXED) return OSC_ERR_INVALID_ARG;
     if (!osc::host::binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
@@ -352,7 +349,7 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
 
     hipDeviceProp_t prop;
     int occ = 0;
-    const size_t lds = size_t(nbt) * osc::kTileLanes * sizeof(double);
+    const size_t lds = size_t(nbt) * osc::kHistLanes * sizeof(double);
     const bool ok =
         hipGetDeviceProperties(&prop, device) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&osc::batch_kernel<true>),

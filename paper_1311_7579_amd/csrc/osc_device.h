@@ -11,7 +11,12 @@ namespace osc {
 namespace dev {
 
 
-constexpr int kPrefetch = 4;   // events in flight ahead of the one computed
+// Events of one lane computed together in one straight-line block (and
+// loaded one block ahead).  One event per block keeps the register count
+// low enough for six waves per SIMD, which hides latency better than
+// interleaving events within a wave.
+constexpr int kGroup = 1;
+static_assert(kLaneEvents % kGroup == 0, "the group size divides the events per lane");
 
 // ---------------------------------------------------------------------------
 // FP64 sine and cosine of a phase (|x| up to ~1e6 rad).
@@ -179,20 +184,19 @@ template <bool MIXED>
 __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* tab,
                                              double kA, double kL, double E, uint32_t f)
 {
-    const uint32_t a = f & 3u, b = (f >> 2) & 3u;
-    const bool valid = (a < 3u) && (b < 3u) && (f < 32u);
-    const uint32_t idx = valid ? (b * 3u + a) : 0u;
-    const double s = ((f >> 4) & 1u) ? -1.0 : 1.0;
+    // flag byte: alpha bits 0-1, beta bits 2-3, antineutrino bit 4
+    const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
+    const uint32_t idx = min((f & 3u) + 3u * ((f >> 2) & 3u), uint32_t(kChannels - 1));
+    const uint32_t anti = (f << 27) & 0x80000000u;   // sign bit for A and the conjugation
     const Chan c = tab[idx];
-    const double A = s * kA * E;
-    const double dee = (idx == 0u) ? 1.0 : 0.0;          // alpha = beta = e
-    const double dba = (a == b) ? 1.0 : 0.0;
+    const double A = flip_sign(kA * E, anti);
+    const double dba = ((f & 3u) == ((f >> 2) & 3u)) ? 1.0 : 0.0;   // alpha = beta
 
     // amplitude inputs: M_ba and (M^2)_ba (conjugated for antineutrinos)
-    const double mre = fma(A, dee, c.m_re);
-    const double mim = s * c.m_im;
-    const double m2re = fma(A, fma(A, dee, c.g_re), c.m2_re);
-    const double m2im = s * fma(A, c.g_im, c.m2_im);
+    const double mre = fma(A, c.dee, c.m_re);
+    const double mim = flip_sign(c.m_im, anti);
+    const double m2re = fma(A, fma(A, c.dee, c.g_re), c.m2_re);
+    const double m2im = flip_sign(fma(A, c.g_im, c.m2_im), anti);
 
     // matter eigenvalues (FP64 in every tier)
     double l0, l1, l2;
@@ -244,22 +248,23 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
         const float si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
         P = double(sr * sr + si * si);
     }
-    return valid ? P : __builtin_nan("");
+    // invalid flags give a quiet NaN (high word 0x7ff80000)
+    return __hiloint2double(valid ? __double2hiint(P) : 0x7ff80000, __double2loint(P));
 }
 
-// Bin of x: floor(fl(fl(x - lo) / wb)) with under/overflow entries.  The
-// quotient is first formed as fl(x - lo) * fl(1 / wb); that is within 3 ulp
-// of the correctly rounded quotient, so the floors agree unless the product
-// lies within 2^-40 of an integer (the bound for quotients below 2^11).
-// Such lanes are flagged and redone with the correctly rounded division.
+// Bin of x: floor(fl(fl(x * scale - lo) / wb)) with under/overflow.  The
+// quotient is first formed as fl(x * scale - lo) * fl(1 / wb); that is
+// within 3 ulp of the correctly rounded quotient, so the floors agree unless
+// the product lies within 2^-40 of an integer (the bound for quotients below
+// 2^11).  Such lanes are flagged and redone with the correctly rounded
+// division; beyond 2^11 the bin is overflow (or underflow) either way.
 __device__ __forceinline__ double bin_floor_fast(double x, const BinConsts& bc, bool& edge)
 {
 #pragma clang fp contract(off)
     const double d = x * bc.scale - bc.lo;   // scaled energy, then the offset: two roundings
     const double q = d * bc.inv_wb;
     const double k = __builtin_floor(q);
-    const double fr = q - k;
-    edge = (fr < 0x1p-40 || fr > 1.0 - 0x1p-40) && (k > -3.0) && (k < bc.nb + 2.0);
+    edge = (__builtin_fabs((q - k) - 0.5) > 0.5 - 0x1p-40) && (__builtin_fabs(q) < 0x1p11);
     return k;
 }
 
@@ -269,20 +274,28 @@ __device__ __forceinline__ double bin_floor_exact(double x, const BinConsts& bc)
     return __builtin_floor((x * bc.scale - bc.lo) / bc.wb);
 }
 
-__device__ __forceinline__ int bin_index(double k, const BinConsts& bc)
+// Row of floor value k in the LDS histograms: 0 underflow, 1 + k regular,
+// nb + 1 overflow (NaN included: fmin returns the non-NaN operand).
+__device__ __forceinline__ int lds_bin(double k, const BinConsts& bc)
 {
-    return (k < 0.0) ? bc.nb : ((k < double(bc.nb)) ? int(k) : bc.nb + 1);
+    return int(__builtin_fmax(__builtin_fmin(k, double(bc.nb)), -1.0)) + 1;
 }
 
-// Lane-private histogram slot: bin-major rows of 64 lanes, the lane index
-// XOR-swizzled by the bin so that both the per-lane accumulation and the
-// per-bin transposed reads spread over the LDS banks.
-__device__ __forceinline__ int hslot(int bin, int lane)
+// LDS row of output bin r (output order: nb regular bins, underflow, overflow).
+__device__ __forceinline__ int lds_row_of_output(int r, int nb)
 {
-    return bin * kTileLanes + (lane ^ (bin & 31));
+    return r < nb ? r + 1 : (r == nb ? 0 : nb + 1);
 }
 
-// complete binary tree over the 64 lane sums of one bin
+// Histogram accumulator slot: bin-major rows of kHistLanes accumulators,
+// the accumulator index XOR-swizzled by the bin so that both the per-lane
+// accumulation and the per-bin transposed reads spread over the LDS banks.
+__device__ __forceinline__ int hslot(int bin, int acc)
+{
+    return bin * kHistLanes + (acc ^ (bin & (kHistLanes - 1) & 31));
+}
+
+// complete binary tree over the kHistLanes accumulators of one bin
 template <int N, int J0>
 __device__ __forceinline__ double lane_tree(const double* h, int bin)
 {
@@ -318,26 +331,26 @@ __device__ __forceinline__ EventIn load_event(int64_t i, int64_t n, const double
     return v;
 }
 
-// One group of kPrefetch events of a lane: the probabilities are computed
-// in one straight-line block (no guards: lanes past the end of the sample
-// hold dummy inputs), then stored, binned and accumulated in ascending m.
+// One group of kGroup events of a lane: the probabilities are computed in
+// one straight-line block (no guards: lanes past the end of the sample hold
+// dummy inputs), then stored, binned and accumulated in ascending m.
 template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
 __device__ __forceinline__ void tile_group(const SetConsts& sc, const Chan* tab,
                                            const PathConsts& pc, const BinConsts& bc,
                                            double* hist, int lane, int64_t i0, int64_t n,
-                                           const EventIn (&ev)[kPrefetch], double* p_out)
+                                           const EventIn (&ev)[kGroup], double* p_out)
 {
-    double P[kPrefetch], k[kPrefetch];
-    bool edge[kPrefetch];
+    double P[kGroup], k[kGroup];
+    bool edge[kGroup];
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
+    for (int j = 0; j < kGroup; ++j) {
         P[j] = (MODE != kHist) ? event_prob<MIXED>(sc, tab, pc.kA, pc.kL, ev[j].e, ev[j].f)
                                : ev[j].e;
         k[j] = (MODE != kReweight) ? bin_floor_fast(ev[j].x, bc, edge[j]) : 0.0;
     }
     if (WRITE_P) {
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) {
+        for (int j = 0; j < kGroup; ++j) {
             const int64_t i = i0 + int64_t(j) * kTileLanes;
             if (FULL || i < n) p_out[i] = P[j];
         }
@@ -345,24 +358,36 @@ __device__ __forceinline__ void tile_group(const SetConsts& sc, const Chan* tab,
     if (MODE == kReweight) return;
     bool any_edge = false;
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) any_edge |= edge[j];
+    for (int j = 0; j < kGroup; ++j) any_edge |= edge[j];
     if (__builtin_expect(any_edge, 0)) {
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j)
+        for (int j = 0; j < kGroup; ++j)
             if (edge[j]) k[j] = bin_floor_exact(ev[j].x, bc);
     }
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
+    for (int j = 0; j < kGroup; ++j) {
         const int64_t i = i0 + int64_t(j) * kTileLanes;
         if (FULL || i < n) {
 #pragma clang fp contract(off)
             const double cval = ev[j].w * P[j];            // rounded, never fused
-            const int slot = hslot(bin_index(k[j], bc), lane);
-            hist[slot] = hist[slot] + cval;                // ascending m per lane
+            const int slot = hslot(lds_bin(k[j], bc), lane & (kHistLanes - 1));
+            // The lanes sharing an accumulator add in ascending lane order:
+            // one masked LDS read-add-write per lane group, group after
+            // group.  The DS instructions of a wave execute in order, so a
+            // group reads what the previous group wrote; the empty asm with
+            // a memory clobber keeps the compiler from merging or
+            // reordering the groups (each lane runs only one of them).
+#pragma unroll
+            for (int p = 0; p < kLaneShare; ++p) {
+                if (lane / kHistLanes == p) hist[slot] = hist[slot] + cval;
+                asm volatile("" ::: "memory");
+            }
         }
     }
 }
 
+// The kLaneEvents events of one lane, fully unrolled: the loads of group
+// g + 1 are issued before group g is computed.
 template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
 __device__ __forceinline__ void tile_events(const SetConsts& sc, const Chan* tab,
                                             const PathConsts& pc, const BinConsts& bc,
@@ -371,29 +396,39 @@ __device__ __forceinline__ void tile_events(const SetConsts& sc, const Chan* tab
                                             const double* weight, const double* e_reco,
                                             const double* value, double* p_out)
 {
-    EventIn ring[kPrefetch];
+    constexpr int kGroups = kLaneEvents / kGroup;
+    EventIn ev[kGroups][kGroup];
 #pragma unroll
-    for (int j = 0; j < kPrefetch; ++j)
-        ring[j] = load_event<MODE, FULL>(base + int64_t(j) * kTileLanes, n, e_true, flags,
-                                         weight, e_reco, value);
-    for (int m0 = 0; m0 < kLaneEvents; m0 += kPrefetch) {
-        EventIn cur[kPrefetch];
+    for (int j = 0; j < kGroup; ++j)
+        ev[0][j] = load_event<MODE, FULL>(base + int64_t(j) * kTileLanes, n, e_true, flags,
+                                          weight, e_reco, value);
 #pragma unroll
-        for (int j = 0; j < kPrefetch; ++j) cur[j] = ring[j];
-        if (m0 + kPrefetch < kLaneEvents) {
+    for (int g = 0; g < kGroups; ++g) {
+        if (g + 1 < kGroups) {
 #pragma unroll
-            for (int j = 0; j < kPrefetch; ++j)
-                ring[j] = load_event<MODE, FULL>(base + int64_t(m0 + kPrefetch + j) * kTileLanes,
-                                                 n, e_true, flags, weight, e_reco, value);
+            for (int j = 0; j < kGroup; ++j)
+                ev[g + 1][j] = load_event<MODE, FULL>(
+                    base + int64_t((g + 1) * kGroup + j) * kTileLanes, n, e_true, flags, weight,
+                    e_reco, value);
         }
         tile_group<MODE, WRITE_P, FULL, MIXED>(sc, tab, pc, bc, hist, lane,
-                                        base + int64_t(m0) * kTileLanes, n, cur, p_out);
+                                               base + int64_t(g * kGroup) * kTileLanes, n,
+                                               ev[g], p_out);
     }
+}
+
+// Copy the channel table of a parameter set into LDS (all lanes of the wave).
+__device__ __forceinline__ void load_tab(const SetConsts& sc, Chan* tab, int lane)
+{
+    constexpr int kWords = kChannels * int(sizeof(Chan) / sizeof(double));
+    const double* src = reinterpret_cast<const double*>(sc.ch);
+    double* dst = reinterpret_cast<double*>(tab);
+    for (int i = lane; i < kWords; i += kTileLanes) dst[i] = src[i];
 }
 
 __device__ __forceinline__ void hist_zero(double* hist, int lane, int nbt)
 {
-    for (int bin = 0; bin < nbt; ++bin) hist[hslot(bin, lane)] = 0.0;
+    for (int i = lane; i < nbt * kHistLanes; i += kTileLanes) hist[i] = 0.0;
 }
 
 // Tree over the 64 lanes of every bin of a finished tile, written as row
@@ -402,7 +437,8 @@ __device__ __forceinline__ void tile_write(const double* hist, int lane, int nbt
                                            double* out)
 {
     for (int bin = lane; bin < nbt; bin += kTileLanes)
-        out[partial_index(row, bin, nbt)] = lane_tree<kTileLanes, 0>(hist, bin);
+        out[partial_index(row, bin, nbt)] =
+            lane_tree<kHistLanes, 0>(hist, lds_row_of_output(bin, nbt - 2));
 }
 
 // Adjacent-pair tree across the 64 lanes of a wave (xor butterfly: both
@@ -426,39 +462,29 @@ __device__ __forceinline__ double chunk_sum(const double* __restrict__ src, int6
     return wave_tree(a + b);
 }
 
-// One merge level (see MergeLevel): block (gc, set) reduces chunk gc of the
-// set's input rows, per bin; four bins per wave in flight.
+// One merge level (see MergeLevel): wave w of block (gc, g, set) reduces
+// chunk gc of the set's input rows for bin g * kMergeWaves + w.  One bin per
+// wave keeps every chunk sum of a level in flight at once.
 template <bool FINAL>
 __device__ __forceinline__ void merge_level_block(const MergeLevel& L, const double* __restrict__ in,
                                                   double* __restrict__ out)
 {
-    const int64_t gc = blockIdx.x, set = blockIdx.y;
+    const int nbt = L.nbt;
+    const int b = int(blockIdx.y) * kMergeWaves + int(threadIdx.x >> 6);
+    if (b >= nbt) return;
+    const int64_t gc = blockIdx.x, set = blockIdx.z;
     int s = 0;
     while (s + 1 < L.n_samples && gc >= L.chunk0[s + 1]) ++s;
     const int64_t c = gc - L.chunk0[s];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWaves = kMergeThreads / 64;
-    const int nbt = L.nbt;
-    const double* chunk_base = in + set * L.set_stride_in + gc * int64_t(nbt) * kMergeChunkTiles;
-    for (int b0 = wave; b0 < nbt; b0 += 4 * kWaves) {
-        double r[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + j * kWaves;
-            r[j] = b < nbt ? chunk_sum(chunk_base + int64_t(b) * kMergeChunkTiles,
-                                       c * kMergeChunkTiles, L.rows[s], lane)
-                           : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int b = b0 + j * kWaves;
-            if (lane == 0 && b < nbt) {
-                if (FINAL)
-                    out[(set * L.n_samples + s) * nbt + b] = r[j];
-                else
-                    out[set * L.set_stride_out + partial_index(L.out_row0[s] + c, b, nbt)] = r[j];
-            }
-        }
+    const int lane = threadIdx.x & 63;
+    const double* src =
+        in + set * L.set_stride_in + (gc * int64_t(nbt) + b) * kMergeChunkTiles;
+    const double r = chunk_sum(src, c * kMergeChunkTiles, L.rows[s], lane);
+    if (lane == 0) {
+        if (FINAL)
+            out[(set * L.n_samples + s) * nbt + b] = r;
+        else
+            out[set * L.set_stride_out + partial_index(L.out_row0[s] + c, b, nbt)] = r;
     }
 }
 

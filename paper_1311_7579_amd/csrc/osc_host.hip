@@ -96,19 +96,14 @@ osc::SetConsts osc::host::set_consts(const osc_params& p)
     sc.C0 = dm21 * dm31;                        // sum of principal 2x2 minors of H
     sc.CA = H[1][1].real() + H[2][2].real();    // d c1 / dA
     sc.DA = dm21 * dm31 * std::norm(U[0][0]);   // d det / dA = cofactor_ee(H)
-    const double nan = std::nan("");
-    for (int b = 0; b < 4; ++b)
-        for (int a = 0; a < 4; ++a) {
-            osc::Chan& c = sc.ch[(b << 2) | a];
-            if (a == 3 || b == 3) {
-                c = osc::Chan{nan, nan, nan, nan, nan, nan};
-                continue;
-            }
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
             cplx g = 0.0;
             if (b == 0) g += H[0][a];
             if (a == 0) g += H[b][0];
-            c = osc::Chan{H[b][a].real(), H[b][a].imag(), H2[b][a].real(), H2[b][a].imag(),
-                          g.real(), g.imag()};
+            sc.ch[3 * b + a] = osc::Chan{H[b][a].real(), H[b][a].imag(), H2[b][a].real(),
+                                         H2[b][a].imag(), g.real(),          g.imag(),
+                                         (a == 0 && b == 0) ? 1.0 : 0.0};
         }
     return sc;
 }
@@ -157,13 +152,18 @@ void drop_profile(osc_ctx* ctx)
     ctx->prof.clear();
 }
 
-// Starts a profiling record on `stream` when profiling is on.
+// Starts a profiling record on `stream` when profiling is on.  The timing
+// events skip the system-scope fence (they only bracket kernels on one
+// device), which keeps their own cost out of the measured interval.
 ProfRec* prof_begin(osc_ctx* ctx, hipStream_t stream)
 {
     if (!ctx->profiling) return nullptr;
     ProfRec r;
-    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.mid) != hipSuccess ||
-        hipEventCreate(&r.end) != hipSuccess || hipEventRecord(r.start, stream) != hipSuccess) {
+    const unsigned fl = hipEventDisableSystemFence;
+    if (hipEventCreateWithFlags(&r.start, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&r.mid, fl) != hipSuccess ||
+        hipEventCreateWithFlags(&r.end, fl) != hipSuccess ||
+        hipEventRecord(r.start, stream) != hipSuccess) {
         for (hipEvent_t e : {r.start, r.mid, r.end})
             if (e) (void)hipEventDestroy(e);
         return nullptr;
@@ -322,14 +322,14 @@ osc_status osc_create(osc_ctx** out, int device)
     ctx->device = device;
     // per-lane histograms: (nbins + 2) x 64 lanes x 8 B of dynamic LDS,
     // next to the 9-entry channel table
-    const size_t static_lds = 9 * sizeof(osc::Chan);
+    const size_t static_lds = osc::kChannels * sizeof(osc::Chan);
     size_t lds = prop.sharedMemPerBlock > static_lds ? prop.sharedMemPerBlock - static_lds : 0;
     if (osc::set_kernel_attributes(lds) != hipSuccess) {
         // keep to the default 64 KiB per workgroup when the larger limit is refused
         (void)hipGetLastError();
         lds = std::min<size_t>(lds, 65536 - static_lds);
     }
-    const size_t row = size_t(osc::kTileLanes) * sizeof(double);
+    const size_t row = size_t(osc::kHistLanes) * sizeof(double);
     ctx->max_nbins = int32_t(lds / row) - 2;
     ctx->max_dyn_lds = lds;
     if (ctx->max_nbins < 1) {
@@ -489,10 +489,11 @@ osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, con
                                                  static_cast<hipStream_t>(stream)));
 }
 
-void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events)
+void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events, int32_t* accumulators)
 {
     if (tile_lanes) *tile_lanes = osc::kTileLanes;
     if (lane_events) *lane_events = osc::kLaneEvents;
+    if (accumulators) *accumulators = osc::kHistLanes;
 }
 
 int32_t osc_max_nbins(const osc_ctx* ctx) { return ctx ? ctx->max_nbins : 0; }

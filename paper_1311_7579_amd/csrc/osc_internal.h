@@ -11,19 +11,40 @@ namespace osc {
 constexpr int kTileLanes = 64;
 constexpr int kLaneEvents = 16;
 constexpr int kTileEvents = kTileLanes * kLaneEvents;
+// Histogram accumulators per bin of a tile: lane l adds into accumulator
+// l mod kHistLanes, so kLaneShare lanes share one accumulator and add into
+// it in ascending lane order.  Small accumulator rows keep the LDS per wave
+// low (occupancy is bounded by registers, not by the histograms).  The
+// value is part of the reduction contract (the bits of every histogram
+// depend on it); the macro exists for build-time tuning sweeps.
+#ifndef OSC_HIST_LANES
+#define OSC_HIST_LANES 8
+#endif
+constexpr int kHistLanes = OSC_HIST_LANES;
+constexpr int kLaneShare = kTileLanes / kHistLanes;
+// Waves per SIMD the per-event kernels are compiled for (register caps
+// that the compiler meets without spilling).
+#ifndef OSC_TILE_WAVES
+#define OSC_TILE_WAVES 6
+#endif
+constexpr int kTileWavesPerSimd = OSC_TILE_WAVES;
+constexpr int kBatchWavesPerSimd = 4;
 
 // Largest event count accepted.
 constexpr int64_t kMaxEvents = int64_t(1) << 32;
-// Histogram merge: launches of 256-thread blocks, each reducing an aligned
-// chunk of kMergeChunkTiles rows (tile results, then chunk results) per bin,
+// Histogram merge: launches in which each wave reduces an aligned chunk of
+// kMergeChunkTiles rows (tile results, then chunk results) of one bin,
 // level by level until one row per histogram is left.  Rows are stored
 // bin-major within each chunk (partial_index).
 constexpr int kMergeThreads = 256;
+constexpr int kMergeWaves = kMergeThreads / 64;
 constexpr int kMergeChunkTiles = 128;
 constexpr int kMaxBatchSamples = 16;
+// Largest number of parameter sets of one batch (the merge grid's z extent).
+constexpr int kMaxBatchSets = 65535;
 
 // One level of the merge for n_samples samples (x any number of parameter
-// sets, one set per grid row): sample s has rows[s] input rows stored from
+// sets, one set per grid layer z): sample s has rows[s] input rows stored from
 // row 128 * chunk0[s] of the set's input region and produces
 // ceil(rows[s] / 128) (at least one) output rows, stored from row
 // out_row0[s] of the set's output region.  The final level writes
@@ -51,18 +72,24 @@ __host__ __device__ inline int64_t partial_index(int64_t tile, int bin, int nbt)
 //   M_ba      = m + A [a = b = e]
 //   (M^2)_ba  = m2 + A g + A^2 [a = b = e],  g = [b = e] H0_ea + H0_be [a = e]
 // Antineutrinos use the complex conjugates and the opposite sign of A.
+// dee = [a = b = e] is stored as 0.0 / 1.0 so that the kernel applies it
+// with FMAs.  (Seven doubles: the 9-entry table stays within 512 bytes of
+// LDS, the allocation granule, next to the histograms.)
 struct Chan {
     double m_re, m_im;
     double m2_re, m2_im;
     double g_re, g_im;
+    double dee;
 };
+
+constexpr int kChannels = 9;   // index 3 beta + alpha
 
 // Parameter-only quantities of one oscillation parameter set.
 // Characteristic polynomial of M: x^3 - tr x^2 + c1 x - det with
 //   tr = T0 + A,  c1 = C0 + A CA,  det = A DA.
 struct SetConsts {
     double T0, C0, CA, DA;
-    Chan ch[16];   // index (beta << 2) | alpha; entries with a 3 hold NaN
+    Chan ch[kChannels];
 };
 
 // Path constants of one sample.
@@ -78,5 +105,9 @@ struct BinConsts {
     double scale;   // 1 + e_scale rounded to FP64; the bin is taken for x * scale
     int32_t nb;     // regular bins; entries nb and nb + 1 are under/overflow
 };
+
+// Flag bytes f < 32 with alpha = f & 3 < 3 and beta = (f >> 2) & 3 < 3, as
+// a bit mask over f.
+constexpr uint32_t kValidFlags = 0x07770777u;
 
 }  // namespace osc

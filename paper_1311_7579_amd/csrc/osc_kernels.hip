@@ -2,7 +2,7 @@
 //
 // One wave64 owns one tile of kTileEvents consecutive events.  Lane l of
 // tile t handles events t*T + m*64 + l, m = 0..K-1 (coalesced SoA loads,
-// software-pipelined kPrefetch events ahead), computes the oscillation
+// software-pipelined one group of kGroup events ahead), computes the oscillation
 // probability of each event in FP64 (flavour basis, one amplitude element
 // per event), optionally writes it, and adds w * P into a lane-private
 // histogram held in LDS.  The 64 lane histograms of the tile meet in a
@@ -22,8 +22,10 @@ namespace {
 
 using namespace dev;
 
+// Register budget for kTileWavesPerSimd resident waves per SIMD.
 template <int MODE, bool WRITE_P, bool MIXED = false>
-__global__ __launch_bounds__(kTileLanes) void tile_kernel(
+__global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kTileWavesPerSimd)))
+void tile_kernel(
     SetConsts sc, PathConsts pc, BinConsts bc, int64_t n, int64_t ntiles,
     const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
     const double* __restrict__ weight, const double* __restrict__ e_reco,
@@ -31,21 +33,14 @@ __global__ __launch_bounds__(kTileLanes) void tile_kernel(
     double* __restrict__ partial)
 {
     extern __shared__ double hist[];
-    __shared__ Chan tab[9];
+    __shared__ Chan tab[kChannels];
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kTileEvents + lane;
     const int nbt = bc.nb + 2;
 
-    if (MODE != kHist) {
-        if (lane == 0) {
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) tab[b * 3 + a] = sc.ch[(b << 2) | a];
-        }
-    }
+    if (MODE != kHist) load_tab(sc, tab, lane);
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
@@ -113,7 +108,7 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
 {
     const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
     if (ntiles == 0) return hipSuccess;
-    const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kTileLanes * sizeof(double);
+    const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
     const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
 #define OSC_LAUNCH(M, W, X)                                                                      \
     hipLaunchKernelGGL((tile_kernel<M, W, X>), grid, block, lds, stream, sc, pc, bc, n, ntiles,  \
@@ -184,7 +179,8 @@ hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, dou
     const double* in = scratch;
     for (size_t l = 0; l < p.levels.size(); ++l) {
         const MergeLevel& L = p.levels[l];
-        const dim3 grid{unsigned(L.total_chunks), unsigned(n_sets)};
+        const dim3 grid{unsigned(L.total_chunks), unsigned((p.nbt + kMergeWaves - 1) / kMergeWaves),
+                        unsigned(n_sets)};
         const bool final_level = l + 1 == p.levels.size();
         double* out = final_level ? hist_out : bufs[l % 2];
         if (final_level)
@@ -202,7 +198,7 @@ hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, dou
 
 hipError_t occupancy(int mode, int nbins, int* blocks_per_cu)
 {
-    const size_t lds = mode == kReweight ? 0 : size_t(nbins + 2) * kTileLanes * sizeof(double);
+    const size_t lds = mode == kReweight ? 0 : size_t(nbins + 2) * kHistLanes * sizeof(double);
     const void* f = mode == kReweight ? reinterpret_cast<const void*>(&tile_kernel<kReweight, true>)
                   : mode == kPdf      ? reinterpret_cast<const void*>(&tile_kernel<kPdf, true>)
                                       : reinterpret_cast<const void*>(&tile_kernel<kHist, false>);

@@ -111,7 +111,7 @@ def load():
     L.osc_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.osc_profile_read.restype = st
-    L.osc_reduction_layout.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.osc_reduction_layout.argtypes = [ctypes.POINTER(i32)] * 3
     L.osc_reduction_layout.restype = None
     L.osc_occupancy.argtypes = [vp, i32, ctypes.c_int, ctypes.POINTER(i32)]
     L.osc_occupancy.restype = st
@@ -197,9 +197,9 @@ def _stream(stream):
 
 
 def osc_reduction_layout():
-    w, k = ctypes.c_int32(), ctypes.c_int32()
-    load().osc_reduction_layout(ctypes.byref(w), ctypes.byref(k))
-    return w.value, k.value
+    w, k, a = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    load().osc_reduction_layout(ctypes.byref(w), ctypes.byref(k), ctypes.byref(a))
+    return w.value, k.value, a.value
 
 
 def osc_validate_params(sets) -> int:

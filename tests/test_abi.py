@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_reduction_layout_matches_oracle_contract(lib):
-    assert osc.osc_reduction_layout() == (oracle.CONTRACT_W, oracle.CONTRACT_K)
+    assert osc.osc_reduction_layout() == (oracle.CONTRACT_W, oracle.CONTRACT_K, oracle.CONTRACT_A)
 
 
 def test_status_strings(lib):

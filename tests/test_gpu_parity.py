@@ -72,9 +72,9 @@ def gpu_fill_pdf(osc, ctx, s, nbins, lo, hi, set_index=0, want_p=True):
 
 
 def hist_tolerance(w, c, bins, nbt, n):
-    W, K = oracle.CONTRACT_W, oracle.CONTRACT_K
+    W, K, A = oracle.CONTRACT_W, oracle.CONTRACT_K, oracle.CONTRACT_A
     ntiles = max(1, -(-n // (W * K)))
-    depth = K + int(math.log2(W)) + math.ceil(math.log2(ntiles)) + 1
+    depth = K * W // A + int(math.log2(A)) + math.ceil(math.log2(ntiles)) + 1
     sw = np.bincount(bins, weights=np.abs(w), minlength=nbt)
     sc = np.bincount(bins, weights=np.abs(c), minlength=nbt)
     return P_TOL * sw + 2 * depth * 2.0 ** -53 * sc

@@ -69,8 +69,25 @@ def test_contract_lane_order_single_tile():
     reversed_m = _seq([c[6], c[4], c[2], c[0]]) + _seq([c[7], c[5], c[3], c[1]])
     naive = _seq(c)
     assert want != transposed and want != reversed_m and want != naive
-    got = oracle.hist_contract(c, np.zeros(8, np.int32), 1, W=2, K=4)
+    got = oracle.hist_contract(c, np.zeros(8, np.int32), 1, W=2, K=4, A=2)
     assert got[0] == want
+
+
+def test_contract_shared_accumulators():
+    # W = 4 lanes, K = 2, A = 2 accumulators: lanes 0 and 2 share accumulator
+    # 0, lanes 1 and 3 accumulator 1; additions in ascending m, then lane
+    big = 2.0 ** 53
+    c = [1.0, 1.0, big, big, 1.0, 1.0, 3.0, 1.0]
+    acc0 = _seq([c[0], c[2], c[4], c[6]])      # m = 0: lanes 0, 2; m = 1: lanes 0, 2
+    acc1 = _seq([c[1], c[3], c[5], c[7]])
+    want = acc0 + acc1
+    lane_major = _seq([c[0], c[4], c[2], c[6]]) + _seq([c[1], c[5], c[3], c[7]])
+    private = (_seq([c[0], c[4]]) + _seq([c[1], c[5]])) + (_seq([c[2], c[6]]) + _seq([c[3], c[7]]))
+    assert want != lane_major and want != private
+    got = oracle.hist_contract(c, np.zeros(8, np.int32), 1, W=4, K=2, A=2)
+    assert got[0] == want
+    with pytest.raises(ValueError):
+        oracle.hist_contract(c, np.zeros(8, np.int32), 1, W=4, K=2, A=3)
 
 
 def test_contract_tile_tree_with_padding():
@@ -78,12 +95,12 @@ def test_contract_tile_tree_with_padding():
     c4 = [0.5, 0.75, 2.0 ** 53, 1.0]
     want4 = (c4[0] + c4[1]) + (c4[2] + c4[3])
     assert want4 != _seq(c4) and want4 != _seq(c4[::-1])
-    assert oracle.hist_contract(c4, np.zeros(4, np.int32), 1, W=1, K=1)[0] == want4
+    assert oracle.hist_contract(c4, np.zeros(4, np.int32), 1, W=1, K=1, A=1)[0] == want4
 
     c5 = [0.75, 5.0, 2.0 ** 53, 3.0, 0.75]
     want5 = ((c5[0] + c5[1]) + (c5[2] + c5[3])) + ((c5[4] + 0.0) + (0.0 + 0.0))
     assert want5 != _seq(c5) and want5 != _seq(c5[::-1])
-    assert oracle.hist_contract(c5, np.zeros(5, np.int32), 1, W=1, K=1)[0] == want5
+    assert oracle.hist_contract(c5, np.zeros(5, np.int32), 1, W=1, K=1, A=1)[0] == want5
 
 
 def test_contract_lane_tree_and_bins():
@@ -94,7 +111,7 @@ def test_contract_lane_tree_and_bins():
     t0b1 = (0.0 + c[1]) + (0.0 + c[3])
     t1b0 = (0.0 + c[5]) + (0.0 + c[7])
     t1b1 = (c[4] + 0.0) + (c[6] + 0.0)
-    got = oracle.hist_contract(c, b, 2, W=4, K=1)
+    got = oracle.hist_contract(c, b, 2, W=4, K=1, A=4)
     assert got[0] == t0b0 + t1b0
     assert got[1] == t0b1 + t1b1
 
@@ -121,8 +138,9 @@ def test_contract_counts_exact_and_error_bound():
     for k in range(nbt):
         exact = math.fsum(c[b == k])
         nk = int((b == k).sum())
-        # lane chains of <= K, then trees of depth log2(W) + log2(#tiles)
-        depth = oracle.CONTRACT_K + 6 + math.ceil(math.log2(max(2, n / 1024)))
+        # accumulator chains of <= K W / A, then trees of depth log2(A) + log2(#tiles)
+        chain = oracle.CONTRACT_K * oracle.CONTRACT_W // oracle.CONTRACT_A
+        depth = chain + int(math.log2(oracle.CONTRACT_A)) + math.ceil(math.log2(max(2, n / 1024)))
         assert abs(got[k] - exact) <= depth * 2.0 ** -53 * exact, (k, nk)
 
 
