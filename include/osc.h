@@ -161,6 +161,55 @@ osc_status osc_profile_enable(osc_ctx* ctx, int on);
 osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
                             double* merge_kernel_ms, int64_t* merge_kernel_launches);
 
+/* ---- Bin-centre reweighting (Sec. 1.1.1) ----
+ * The approximation that event-by-event reweighting replaces: apply a
+ * parameter set at the centre of each true-energy bin and to the whole
+ * bin.  The sample is reduced once to a migration template
+ *   T[r][c][t] = sum of the weights of the events of channel c in true
+ *                bin t and reconstructed bin r,
+ * channel c = alpha + 3 beta + 9 anti (18 channels), each cell's weights
+ * added in ascending event order from +0.0.  A call then computes
+ *   P[c][t] = P_c(E_t),  E_t = lo_t + (t + 1/2) * ((hi_t - lo_t) / nt)
+ *   hist[r] = sum over k = c nt + t of fl(T[r][k] * P[k]),
+ * the terms of each r in a fixed order: term k goes to lane k mod 64, each
+ * lane adds its terms in ascending k from +0.0, and the 64 lane sums meet
+ * in the complete binary tree over lane index.  The result is
+ * bit-reproducible. */
+typedef struct osc_template osc_template;
+
+/* Build the template of `sample` (device arrays as in osc_sample, n up to
+ * 2^31 - 1; weight and e_reco are read).  true_binning: the true-energy
+ * bins, 1 <= nbins <= 65536, 0 <= lo < hi, e_scale = 0; events whose true
+ * energy falls outside [0, nbins) by the binning rule of osc_binning, and
+ * events with an invalid flag byte, are left out.  reco_binning: as for
+ * osc_fill_pdf (e_scale applies; under/overflow rows kept).  Synchronous:
+ * waits for all earlier work on the device, returns once the template is
+ * built, after which the sample arrays are no
+ * longer read; the path (L, rho, Ye) is taken from `sample`.  *n_used
+ * (may be NULL) receives the number of events in the template.  The
+ * template holds (nbins_reco + 2) * 18 * nbins_true FP64 values of device
+ * memory and belongs to ctx. */
+osc_status osc_template_create(osc_ctx* ctx, const osc_sample* sample,
+                               const osc_binning* true_binning,
+                               const osc_binning* reco_binning, osc_template** out,
+                               int64_t* n_used);
+
+/* Wait for the device and free the template. NULL is accepted. */
+osc_status osc_template_destroy(osc_template* t);
+
+/* Copy the template, layout [r][c][t], to dst (device, (nbins_reco + 2) *
+ * 18 * nbins_true FP64 entries) on `stream`. */
+osc_status osc_template_copy(const osc_template* t, double* dst, void* stream);
+
+/* Bin-centre PDF of parameter set `set`: hist_out (device, nbins_reco + 2
+ * entries, overwritten).  p_centre_out (device, 18 * nbins_true entries,
+ * layout [c][t]) may be NULL; when given it receives the probabilities at
+ * the bin centres and serves as the call's table.  Without it the table is
+ * the template's own buffer, so calls on one template without
+ * p_centre_out must not overlap (one stream at a time). */
+osc_status osc_fill_pdf_bincentre(osc_ctx* ctx, const osc_template* t, int32_t set,
+                                  double* hist_out, double* p_centre_out, void* stream);
+
 /* Sec. 2.2, Eq. (2): the binned likelihood of the fitter, read as a
  * product over the regular bins of Poisson probabilities of observed counts
  * d_b given the PDF mu_b:  -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)

@@ -73,6 +73,11 @@ def lib():
         L.oracle_bin_index_scaled.restype = i32
         L.oracle_fill_pdf.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_template.argtypes = [i64, vp, vp, vp, vp, i32, d, d, i32, d, d, d, vp, vp]
+        L.oracle_bin_centre.argtypes = [d, d, i32, i32]
+        L.oracle_bin_centre.restype = d
+        L.oracle_centre_probs.argtypes = [P, d, d, d, i32, d, d, vp]
+        L.oracle_bincentre_contract.argtypes = [vp, vp, i32, i32, vp]
         L.oracle_poisson_nll.argtypes = [vp, vp, i32]
         L.oracle_poisson_nll.restype = d
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
@@ -156,6 +161,52 @@ def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K, A=CONTRACT_A) -> np.
     lib().oracle_hist_contract(_ptr(c), _ptr(b), c.size, int(nbt), int(W), int(K), int(A),
                                _ptr(out))
     return out
+
+
+N_CHANNELS = 18   # alpha + 3 beta + 9 anti
+
+
+def template(e_true, flags, weight, e_reco, nt, lo_t, hi_t, nr, lo_r, hi_r, e_scale=0.0):
+    """Migration template T[r][c][t] of the bin-centre method and the number
+    of events it holds."""
+    e = np.ascontiguousarray(e_true, dtype=np.float64)
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    w = np.ascontiguousarray(weight, dtype=np.float64)
+    r = np.ascontiguousarray(e_reco, dtype=np.float64)
+    if not (e.shape == f.shape == w.shape == r.shape):
+        raise ValueError("event arrays differ in length")
+    T = np.zeros((int(nr) + 2, N_CHANNELS, int(nt)), dtype=np.float64)
+    used = ctypes.c_int64()
+    lib().oracle_template(e.size, _ptr(e), _ptr(f), _ptr(w), _ptr(r), int(nt), float(lo_t),
+                          float(hi_t), int(nr), float(lo_r), float(hi_r), float(e_scale), _ptr(T),
+                          ctypes.byref(used))
+    return T, used.value
+
+
+def bin_centre(lo, hi, nt, t) -> float:
+    return lib().oracle_bin_centre(float(lo), float(hi), int(nt), int(t))
+
+
+def centre_probs(params, L_km, rho, Ye, nt, lo_t, hi_t) -> np.ndarray:
+    """P[c][t] at the true-bin centres for the 18 channels."""
+    P = np.zeros((N_CHANNELS, int(nt)), dtype=np.float64)
+    pp = to_params(params)
+    lib().oracle_centre_probs(ctypes.byref(pp), float(L_km), float(rho), float(Ye), int(nt),
+                              float(lo_t), float(hi_t), _ptr(P))
+    return P
+
+
+def bincentre_contract(T, P) -> np.ndarray:
+    """hist[r] = sum_k fl(T[r][k] P[k]) in the lane-strided tree order."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    nrt = T.shape[0]
+    K = P.size
+    if T.size != nrt * K:
+        raise ValueError("template and probability table do not match")
+    hist = np.zeros(nrt, dtype=np.float64)
+    lib().oracle_bincentre_contract(_ptr(T), _ptr(P), int(K), int(nrt), _ptr(hist))
+    return hist
 
 
 def poisson_nll(mu, data) -> float:

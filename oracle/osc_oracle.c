@@ -308,6 +308,60 @@ void oracle_hist_contract(const double* c, const int32_t* bin, int64_t n,
     free(tiles);
 }
 
+void oracle_template(int64_t n, const double* e_true, const uint8_t* flags,
+                     const double* weight, const double* e_reco,
+                     int32_t nt, double lo_t, double hi_t,
+                     int32_t nr, double lo_r, double hi_r, double e_scale,
+                     double* T, int64_t* n_used)
+{
+    const int64_t K = 18 * (int64_t)nt;
+    for (int64_t q = 0; q < (int64_t)(nr + 2) * K; ++q) T[q] = 0.0;
+    int64_t used = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int alpha = flags[i] & 3, beta = (flags[i] >> 2) & 3, anti = (flags[i] >> 4) & 1;
+        if (flags[i] >= 32 || alpha == 3 || beta == 3) continue;
+        const int32_t t = oracle_bin_index(e_true[i], lo_t, hi_t, nt);
+        if (t >= nt) continue;   /* underflow (nt) or overflow (nt + 1) */
+        const int32_t r = oracle_bin_index_scaled(e_reco[i], e_scale, lo_r, hi_r, nr);
+        const int64_t c = alpha + 3 * beta + 9 * anti;
+        T[(int64_t)r * K + c * nt + t] += weight[i];
+        ++used;
+    }
+    if (n_used) *n_used = used;
+}
+
+double oracle_bin_centre(double lo, double hi, int32_t nt, int32_t t)
+{
+    const double wb = (hi - lo) / (double)nt;
+    const double off = ((double)t + 0.5) * wb;
+    return lo + off;
+}
+
+void oracle_centre_probs(const oracle_params* p, double L_km, double rho, double Ye,
+                         int32_t nt, double lo_t, double hi_t, double* P)
+{
+    for (int c = 0; c < 18; ++c) {
+        const int alpha = c % 3, beta = (c / 3) % 3, anti = c / 9;
+        for (int32_t t = 0; t < nt; ++t)
+            P[(int64_t)c * nt + t] = oracle_prob(p, L_km, rho, Ye, oracle_bin_centre(lo_t, hi_t, nt, t),
+                                                alpha, beta, anti);
+    }
+}
+
+void oracle_bincentre_contract(const double* T, const double* P, int32_t K, int32_t nrt,
+                               double* hist)
+{
+    double lanes[64];
+    for (int32_t r = 0; r < nrt; ++r) {
+        for (int l = 0; l < 64; ++l) lanes[l] = 0.0;
+        for (int32_t k = 0; k < K; ++k) {
+            const double term = T[(int64_t)r * K + k] * P[k];
+            lanes[k % 64] += term;
+        }
+        hist[r] = tree_sum(lanes, 64, 64);
+    }
+}
+
 double oracle_poisson_nll(const double* mu, const double* data, int32_t nbins)
 {
     double s = 0.0;

@@ -102,6 +102,39 @@ int oracle_fill_pdf(const oracle_params* p, double L_km, double rho, double Ye,
                     int32_t nbins, double lo, double hi, double e_scale, int32_t W, int32_t K,
                     int32_t A, double* hist_out, double* p_out);
 
+/* ---- Bin-centre reweighting (Sec. 1.1.1): the approximation that the
+ * event-by-event method replaces.  The sample is reduced once to a
+ * migration template; a parameter set is then applied through P evaluated
+ * at the centre of each true-energy bin.
+ *
+ * Channel c = alpha + 3 beta + 9 anti (18 channels).  True bin t of E by
+ * oracle_bin_index(E, lo_t, hi_t, nt) (events outside [0, nt), and events
+ * with an invalid flag byte, are left out); reconstructed bin r by
+ * oracle_bin_index_scaled(e_reco, e_scale, lo_r, hi_r, nr), r in
+ * [0, nr + 2).  Template layout T[r][c][t] (reco-bin major): the weights of
+ * the cell's events summed in ascending event order from +0.0.  *n_used
+ * receives the number of events in the template. */
+void oracle_template(int64_t n, const double* e_true, const uint8_t* flags,
+                     const double* weight, const double* e_reco,
+                     int32_t nt, double lo_t, double hi_t,
+                     int32_t nr, double lo_r, double hi_r, double e_scale,
+                     double* T, int64_t* n_used);
+
+/* Centre of true bin t: lo + (t + 1/2) * ((hi - lo) / nt), FP64, the
+ * width and each operation rounded separately. */
+double oracle_bin_centre(double lo, double hi, int32_t nt, int32_t t);
+
+/* P_c(E_t) for the 18 channels at every true-bin centre, layout P[c][t]. */
+void oracle_centre_probs(const oracle_params* p, double L_km, double rho, double Ye,
+                         int32_t nt, double lo_t, double hi_t, double* P);
+
+/* hist[r] = sum over k = c nt + t of fl(T[r][k] * P[k]) for r in [0, nrt):
+ * term k goes to lane k mod 64, each lane adds its terms in ascending k
+ * from +0.0, and the 64 lane sums meet in the complete binary tree over
+ * lane index (adjacent pairs first). */
+void oracle_bincentre_contract(const double* T, const double* P, int32_t K, int32_t nrt,
+                               double* hist);
+
 /* Sec. 2.2, Eq. (2), read as a product over the regular bins of Poisson
  * probabilities of the observed counts d_b given the expectations mu_b:
  * -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)  (ln d! = lgamma(d + 1)).

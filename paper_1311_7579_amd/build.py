@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libosc.so")
-SOURCES = ["osc_host.hip", "osc_kernels.hip", "osc_batch.hip", "osc_serve.hip"]
+SOURCES = ["osc_host.hip", "osc_kernels.hip", "osc_batch.hip", "osc_serve.hip", "osc_template.hip"]
 ARCH = os.environ.get("OSC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

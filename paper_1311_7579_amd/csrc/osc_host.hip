@@ -250,6 +250,14 @@ osc::BinConsts osc::host::bin_consts(const osc_binning* b)
 
 int osc::host::ctx_device(const osc_ctx* ctx) { return ctx->device; }
 
+bool osc::host::ctx_set(osc_ctx* ctx, int32_t set, osc::SetConsts* out)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return false;
+    *out = ctx->consts[size_t(set)];
+    return true;
+}
+
 size_t osc::host::fill_scratch_bytes(int64_t n, int nbins)
 {
     const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;

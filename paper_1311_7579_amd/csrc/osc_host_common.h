@@ -16,6 +16,8 @@ BinConsts bin_consts(const osc_binning* b);
 bool sample_ok(const osc_sample* s, bool needs_hist_inputs);
 bool binning_ok(const osc_ctx* ctx, const osc_binning* b);
 int ctx_device(const osc_ctx* ctx);
+// Copy of parameter set `set` of the context; false when out of range.
+bool ctx_set(osc_ctx* ctx, int32_t set, SetConsts* out);
 
 // Device scratch one osc_fill_pdf-style histogram of n events needs.
 size_t fill_scratch_bytes(int64_t n, int nbins);

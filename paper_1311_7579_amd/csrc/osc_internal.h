@@ -9,7 +9,10 @@ namespace osc {
 // Reduction contract of the binned PDF: a tile is kTileLanes lanes x
 // kLaneEvents events per lane (one wave64 per tile).
 constexpr int kTileLanes = 64;
-constexpr int kLaneEvents = 16;
+#ifndef OSC_LANE_EVENTS
+#define OSC_LANE_EVENTS 16
+#endif
+constexpr int kLaneEvents = OSC_LANE_EVENTS;
 constexpr int kTileEvents = kTileLanes * kLaneEvents;
 // Histogram accumulators per bin of a tile: lane l adds into accumulator
 // l mod kHistLanes, so kLaneShare lanes share one accumulator and add into

@@ -122,6 +122,16 @@ def load():
     L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                    ctypes.c_int, i32, ctypes.POINTER(vp)]
     L.osc_batch_create.restype = st
+    L.osc_template_create.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_binning),
+                                      ctypes.POINTER(osc_binning), ctypes.POINTER(vp),
+                                      ctypes.POINTER(i64)]
+    L.osc_template_create.restype = st
+    L.osc_template_destroy.argtypes = [vp]
+    L.osc_template_destroy.restype = st
+    L.osc_template_copy.argtypes = [vp, vp, vp]
+    L.osc_template_copy.restype = st
+    L.osc_fill_pdf_bincentre.argtypes = [vp, vp, i32, vp, vp, vp]
+    L.osc_fill_pdf_bincentre.restype = st
     L.osc_batch_destroy.argtypes = [vp]
     L.osc_batch_destroy.restype = st
     L.osc_batch_get_config.argtypes = [vp, ctypes.POINTER(osc_batch_config)]
@@ -316,6 +326,53 @@ class Context:
         _check(load().osc_fill_hist(self.handle, n, _ptr(value), _ptr(weight), _ptr(e_reco),
                                     ctypes.byref(b), _ptr(hist_out), _stream(stream)),
                "osc_fill_hist")
+
+
+N_CHANNELS = 18   # alpha + 3 beta + 9 anti
+
+
+class Template:
+    """osc_template: the migration template of the bin-centre method
+    (Sec. 1.1.1) and its per-call PDF."""
+
+    def __init__(self, ctx: Context, sample: "DeviceSample", nt, lo_t, hi_t, nr, lo_r, hi_r,
+                 e_scale=0.0):
+        self.ctx = ctx
+        self.nt, self.nr = int(nt), int(nr)
+        cs = sample.c_struct()
+        tb = osc_binning(self.nt, float(lo_t), float(hi_t), 0.0)
+        rb = osc_binning(self.nr, float(lo_r), float(hi_r), float(e_scale))
+        h = ctypes.c_void_p()
+        used = ctypes.c_int64()
+        _check(load().osc_template_create(ctx.handle, ctypes.byref(cs), ctypes.byref(tb),
+                                          ctypes.byref(rb), ctypes.byref(h), ctypes.byref(used)),
+               "osc_template_create")
+        self.handle = h
+        self.n_used = used.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().osc_template_destroy(self.handle), "osc_template_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def copy(self, stream=None):
+        """The template (nr + 2, 18, nt) on the device."""
+        import torch
+        out = torch.empty((self.nr + 2, N_CHANNELS, self.nt), dtype=torch.float64, device="cuda")
+        _check(load().osc_template_copy(self.handle, _ptr(out), _stream(stream)),
+               "osc_template_copy")
+        return out
+
+    def fill_pdf(self, set_index, hist_out, p_centre_out=None, stream=None):
+        _check(load().osc_fill_pdf_bincentre(self.ctx.handle, self.handle, int(set_index),
+                                             _ptr(hist_out), _ptr(p_centre_out),
+                                             _stream(stream)), "osc_fill_pdf_bincentre")
 
 
 class Batch:
