@@ -161,6 +161,33 @@ osc_status osc_profile_enable(osc_ctx* ctx, int on);
 osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* event_kernel_launches,
                             double* merge_kernel_ms, int64_t* merge_kernel_launches);
 
+/* ---- Piecewise-constant matter ----
+ * The paper takes one constant density (Sec. 1.1); a path through layers
+ * of different densities (the extension the paper's CPU library, Prob3++,
+ * makes for paths through the Earth) evolves the neutrino with the
+ * product of the layers' evolution operators, each the constant-density
+ * operator of Sec. 1.1 for its own density and length:
+ *   S = S_{n-1} ... S_1 S_0,  P(alpha -> beta) = |S_{beta alpha}|^2,
+ * layer 0 crossed first.  Computed in FP64 by propagating column alpha
+ * through the layers. */
+typedef struct {
+    double L_km;     /* layer length, >= 0 */
+    double rho_gcc;  /* density, >= 0      */
+    double Ye;       /* electrons per nucleon, 0..1 */
+} osc_layer;
+
+/* osc_reweight through n_layers (1..32) layers, host array, copied; the
+ * sample's own L_km, rho_gcc and Ye are not used. */
+osc_status osc_reweight_layered(osc_ctx* ctx, const osc_sample* sample, const osc_layer* layers,
+                                int32_t n_layers, int32_t set, double* p_out, void* stream);
+
+/* osc_fill_pdf (FP64) through n_layers layers: same binning rule, same
+ * reduction contract, so the histogram is bit-identical to osc_fill_hist
+ * applied to the P it computes. */
+osc_status osc_fill_pdf_layered(osc_ctx* ctx, const osc_sample* sample, const osc_layer* layers,
+                                int32_t n_layers, int32_t set, const osc_binning* binning,
+                                double* hist_out, double* p_out, void* stream);
+
 /* ---- Bin-centre reweighting (Sec. 1.1.1) ----
  * The approximation that event-by-event reweighting replaces: apply a
  * parameter set at the centre of each true-energy bin and to the whole

@@ -73,6 +73,10 @@ def lib():
         L.oracle_bin_index_scaled.restype = i32
         L.oracle_fill_pdf.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_prob_layered.argtypes = [P, i32, vp, vp, vp, d, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int]
+        L.oracle_prob_layered.restype = d
+        L.oracle_prob_layered_batch.argtypes = [P, i32, vp, vp, vp, i64, vp, vp, vp]
         L.oracle_template.argtypes = [i64, vp, vp, vp, vp, i32, d, d, i32, d, d, d, vp, vp]
         L.oracle_bin_centre.argtypes = [d, d, i32, i32]
         L.oracle_bin_centre.restype = d
@@ -160,6 +164,31 @@ def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K, A=CONTRACT_A) -> np.
     out = np.zeros(int(nbt), dtype=np.float64)
     lib().oracle_hist_contract(_ptr(c), _ptr(b), c.size, int(nbt), int(W), int(K), int(A),
                                _ptr(out))
+    return out
+
+
+def _layers(layers):
+    a = np.ascontiguousarray(np.asarray(layers, dtype=np.float64).reshape(-1, 3))
+    return (np.ascontiguousarray(a[:, 0]), np.ascontiguousarray(a[:, 1]),
+            np.ascontiguousarray(a[:, 2]))
+
+
+def prob_layered(params, layers, E, alpha, beta, anti) -> float:
+    """P through layers [(L_km, rho, Ye), ...], the first crossed first."""
+    L, r, y = _layers(layers)
+    pp = to_params(params)
+    return lib().oracle_prob_layered(ctypes.byref(pp), L.size, _ptr(L), _ptr(r), _ptr(y),
+                                     float(E), int(alpha), int(beta), int(anti))
+
+
+def prob_layered_batch(params, layers, E, flags) -> np.ndarray:
+    L, r, y = _layers(layers)
+    e = np.ascontiguousarray(E, dtype=np.float64)
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    out = np.empty_like(e)
+    pp = to_params(params)
+    lib().oracle_prob_layered_batch(ctypes.byref(pp), L.size, _ptr(L), _ptr(r), _ptr(y), e.size,
+                                    _ptr(e), _ptr(f), _ptr(out))
     return out
 
 

@@ -126,8 +126,10 @@ static void mat_mul(double complex A[3][3], double complex B[3][3],
 }
 
 /* ---- the matter path (Sec. 1.1 matter effects, Sec. 2.1) ---------------- */
-static double prob_matter(double complex U[3][3], const double m2[3], double A,
-                          double L_km, double E, int alpha, int beta)
+/* Evolution operator over L at constant density in the flavour basis,
+ * Sf[beta][alpha] = amplitude alpha -> beta. */
+static void evolution_flavour(double complex U[3][3], const double m2[3], double A,
+                              double L_km, double E, double complex Sf[3][3])
 {
     /* Matter-modified mass matrix (2E times the Hamiltonian) in the mass
      * basis: M_ij = m_i^2 delta_ij + A conj(U_ei) U_ej. */
@@ -184,11 +186,18 @@ static double prob_matter(double complex U[3][3], const double m2[3], double A,
 
     /* Back to the flavour basis: S_f = U S U^dagger; amplitude alpha->beta
      * is S_f[beta][alpha]. */
-    double complex Ud[3][3], T[3][3], Sf[3][3];
+    double complex Ud[3][3], T[3][3];
     for (int r0 = 0; r0 < 3; ++r0)
         for (int c0 = 0; c0 < 3; ++c0) Ud[r0][c0] = conj(U[c0][r0]);
     mat_mul(U, S, T);
     mat_mul(T, Ud, Sf);
+}
+
+static double prob_matter(double complex U[3][3], const double m2[3], double A,
+                          double L_km, double E, int alpha, int beta)
+{
+    double complex Sf[3][3];
+    evolution_flavour(U, m2, A, L_km, E, Sf);
     const double complex amp = Sf[beta][alpha];
     return creal(amp) * creal(amp) + cimag(amp) * cimag(amp);
 }
@@ -203,6 +212,43 @@ double oracle_prob(const oracle_params* p, double L_km, double rho, double Ye,
     /* antineutrinos: U -> conj(U) (done in pmns) and A -> -A */
     const double A = (anti ? -1.0 : 1.0) * oracle_k_matter() * Ye * rho * E;
     return prob_matter(U, m2, A, L_km, E, alpha, beta);
+}
+
+double oracle_prob_layered(const oracle_params* p, int32_t n_layers, const double* L_km,
+                           const double* rho, const double* Ye, double E,
+                           int alpha, int beta, int anti)
+{
+    double complex U[3][3];
+    double m2[3];
+    pmns(p, anti, U);
+    mass_squares(p, m2);
+    /* S = S_{n-1} ... S_0, the first layer crossed on the right */
+    double complex S[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int32_t k = 0; k < n_layers; ++k) {
+        const double A = (anti ? -1.0 : 1.0) * oracle_k_matter() * Ye[k] * rho[k] * E;
+        double complex Sk[3][3], T[3][3];
+        evolution_flavour(U, m2, A, L_km[k], E, Sk);
+        mat_mul(Sk, S, T);
+        memcpy(S, T, sizeof S);
+    }
+    const double complex amp = S[beta][alpha];
+    return creal(amp) * creal(amp) + cimag(amp) * cimag(amp);
+}
+
+void oracle_prob_layered_batch(const oracle_params* p, int32_t n_layers, const double* L_km,
+                               const double* rho, const double* Ye, int64_t n,
+                               const double* E, const uint8_t* flags, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const uint8_t f = flags[i];
+        const int alpha = f & 3, beta = (f >> 2) & 3, anti = (f >> 4) & 1;
+        out[i] = (alpha > 2 || beta > 2 || (f >> 5) != 0)
+                     ? NAN
+                     : oracle_prob_layered(p, n_layers, L_km, rho, Ye, E[i], alpha, beta, anti);
+    }
 }
 
 static double prob_from_flags(const oracle_params* p, double L_km, double rho,

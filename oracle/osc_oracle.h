@@ -60,6 +60,22 @@ double oracle_prob_vacuum(const oracle_params* p, double L_km, double E,
 double oracle_prob(const oracle_params* p, double L_km, double rho, double Ye,
                    double E, int alpha, int beta, int anti);
 
+/* P(alpha -> beta) through n_layers layers of constant density (lengths
+ * L_km[k], densities rho[k], electron fractions Ye[k]; layer 0 crossed
+ * first): the amplitude is element (beta, alpha) of the product
+ * S_{n-1} ... S_1 S_0 of the layers' flavour-basis evolution operators,
+ * each computed as in oracle_prob.  Not in the paper (its path has one
+ * density); the layered path is the extension its CPU library makes. */
+double oracle_prob_layered(const oracle_params* p, int32_t n_layers, const double* L_km,
+                           const double* rho, const double* Ye, double E,
+                           int alpha, int beta, int anti);
+
+/* oracle_prob_layered over events described by flag bytes (NaN for an
+ * invalid flag byte), OpenMP. */
+void oracle_prob_layered_batch(const oracle_params* p, int32_t n_layers, const double* L_km,
+                               const double* rho, const double* Ye, int64_t n,
+                               const double* E, const uint8_t* flags, double* out);
+
 /* Same as oracle_prob for arrays of events described by flag bytes.
  * OpenMP-parallel over events; returns the thread count used. */
 int oracle_prob_batch(const oracle_params* p, double L_km, double rho, double Ye,

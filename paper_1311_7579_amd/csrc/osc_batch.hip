@@ -100,14 +100,13 @@ void batch_kernel(BatchArgs a,
             load_tab(sc, tab, lane);
             hist_zero(hist, lane, nbt);
             __syncthreads();
+            const ConstDensityProb<MIXED> prob{&sc, tab, S.pc.kA, S.pc.kL};
             if (full)
-                tile_events<kPdf, false, true, MIXED>(sc, tab, S.pc, a.bc, hist, lane, base, S.n,
-                                                      S.e_true, S.flags, S.weight, S.e_reco,
-                                                      nullptr, nullptr);
+                tile_events<kPdf, false, true>(prob, a.bc, hist, lane, base, S.n, S.e_true,
+                                               S.flags, S.weight, S.e_reco, nullptr, nullptr);
             else
-                tile_events<kPdf, false, false, MIXED>(sc, tab, S.pc, a.bc, hist, lane, base, S.n,
-                                                       S.e_true, S.flags, S.weight, S.e_reco,
-                                                       nullptr, nullptr);
+                tile_events<kPdf, false, false>(prob, a.bc, hist, lane, base, S.n, S.e_true,
+                                                S.flags, S.weight, S.e_reco, nullptr, nullptr);
             __syncthreads();
             tile_write(hist, lane, nbt, S.row0 + tile, partial + int64_t(set) * a.set_stride);
         }

@@ -252,6 +252,117 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
     return __hiloint2double(valid ? __double2hiint(P) : 0x7ff80000, __double2loint(P));
 }
 
+// P of one event through one constant-density layer: the policy the tile
+// body calls (MIXED selects the FP32-mixed amplitude assembly).
+template <bool MIXED>
+struct ConstDensityProb {
+    const SetConsts* sc;
+    const Chan* tab;
+    double kA, kL;
+    __device__ __forceinline__ double operator()(double E, uint32_t f) const
+    {
+        return event_prob<MIXED>(*sc, tab, kA, kL, E, f);
+    }
+};
+
+// P(alpha -> beta) of one event through layers of constant density.  The
+// evolution operator of the path is the product of the layers' operators,
+// so only column alpha of it is needed: v = e_alpha is propagated layer by
+// layer.  Within a layer, exp(-i M L / 2E) (common phase dropped) is the
+// polynomial a2 M^2 + a1 M + a0 of its Lagrange form over the eigenvalues,
+//   sum_k c_k (M - l_j)(M - l_l),  c_k = exp(-i dphi_k) / D_k,
+// so v becomes a2 (M M v) + a1 (M v) + a0 v.  M is the flavour-basis mass
+// matrix of the layer (H0 + A e_e e_e^T, conjugated with A -> -A for
+// antineutrinos); its entries come from the channel table.
+__device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const Chan* tab,
+                                                     const LayerPath& lp, double E, uint32_t f)
+{
+    const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
+    const uint32_t a = min(f & 3u, 2u), b = min((f >> 2) & 3u, 2u);
+    const uint32_t anti = (f << 27) & 0x80000000u;
+    // H0 (conjugated for antineutrinos), row-major; the diagonal is real
+    double hr[3][3], hi[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            hr[i][j] = tab[3 * i + j].m_re;
+            hi[i][j] = flip_sign(tab[3 * i + j].m_im, anti);
+        }
+    double vr[3] = {a == 0u ? 1.0 : 0.0, a == 1u ? 1.0 : 0.0, a == 2u ? 1.0 : 0.0};
+    double vi[3] = {0.0, 0.0, 0.0};
+    const double invE = recip(E);
+    for (int layer = 0; layer < lp.n; ++layer) {
+        const PathConsts pc = lp.layer[layer];
+        const double A = flip_sign(pc.kA * E, anti);
+        double l0, l1, l2;
+        cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA, l0, l1, l2);
+        const double d01 = l0 - l1, d02 = l0 - l2, d12 = l1 - l2;
+        const double invQ = recip(d01 * d02 * d12);
+        const double ph = pc.kL * invE;
+        double s1, c1, s2, c2;
+        phase_sincos(-d01 * ph, s1, c1);   // phi_1 - phi_0
+        phase_sincos(-d02 * ph, s2, c2);   // phi_2 - phi_0
+        // c_k = exp(-i dphi_k) / D_k (c_0 real)
+        const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
+        const double k1r = c1 * iD1, k1i = -s1 * iD1;
+        const double k2r = c2 * iD2, k2i = -s2 * iD2;
+        const double u0 = l1 + l2, u1 = l0 + l2, u2 = l0 + l1;
+        const double w0 = l1 * l2, w1 = l0 * l2, w2 = l0 * l1;
+        const double a2r = iD0 + k1r + k2r, a2i = k1i + k2i;
+        const double a1r = -(iD0 * u0 + k1r * u1 + k2r * u2), a1i = -(k1i * u1 + k2i * u2);
+        const double a0r = iD0 * w0 + k1r * w1 + k2r * w2, a0i = k1i * w1 + k2i * w2;
+        // y = M v, z = M y
+        double yr[3], yi[3], zr[3], zi[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double sr = (i == 0) ? A * vr[0] : 0.0, si = (i == 0) ? A * vi[0] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                sr = fma(hr[i][j], vr[j], fma(-hi[i][j], vi[j], sr));
+                si = fma(hr[i][j], vi[j], fma(hi[i][j], vr[j], si));
+            }
+            yr[i] = sr;
+            yi[i] = si;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            double sr = (i == 0) ? A * yr[0] : 0.0, si = (i == 0) ? A * yi[0] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                sr = fma(hr[i][j], yr[j], fma(-hi[i][j], yi[j], sr));
+                si = fma(hr[i][j], yi[j], fma(hi[i][j], yr[j], si));
+            }
+            zr[i] = sr;
+            zi[i] = si;
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double nr = a2r * zr[i] - a2i * zi[i] + a1r * yr[i] - a1i * yi[i] +
+                              a0r * vr[i] - a0i * vi[i];
+            const double ni = a2r * zi[i] + a2i * zr[i] + a1r * yi[i] + a1i * yr[i] +
+                              a0r * vi[i] + a0i * vr[i];
+            vr[i] = nr;
+            vi[i] = ni;
+        }
+    }
+    const double br = b == 0u ? vr[0] : (b == 1u ? vr[1] : vr[2]);
+    const double bi = b == 0u ? vi[0] : (b == 1u ? vi[1] : vi[2]);
+    const double P = br * br + bi * bi;
+    return __hiloint2double(valid ? __double2hiint(P) : 0x7ff80000, __double2loint(P));
+}
+
+// P of one event through a layered path (FP64).
+struct LayeredProb {
+    const SetConsts* sc;
+    const Chan* tab;
+    const LayerPath* lp;
+    __device__ __forceinline__ double operator()(double E, uint32_t f) const
+    {
+        return event_prob_layered(*sc, tab, *lp, E, f);
+    }
+};
+
 // Bin of x: floor(fl(fl(x * scale - lo) / wb)) with under/overflow.  The
 // quotient is first formed as fl(x * scale - lo) * fl(1 / wb); that is
 // within 3 ulp of the correctly rounded quotient, so the floors agree unless
@@ -334,18 +445,16 @@ __device__ __forceinline__ EventIn load_event(int64_t i, int64_t n, const double
 // One group of kGroup events of a lane: the probabilities are computed in
 // one straight-line block (no guards: lanes past the end of the sample hold
 // dummy inputs), then stored, binned and accumulated in ascending m.
-template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
-__device__ __forceinline__ void tile_group(const SetConsts& sc, const Chan* tab,
-                                           const PathConsts& pc, const BinConsts& bc,
-                                           double* hist, int lane, int64_t i0, int64_t n,
+template <int MODE, bool WRITE_P, bool FULL, class PROB>
+__device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc, double* hist,
+                                           int lane, int64_t i0, int64_t n,
                                            const EventIn (&ev)[kGroup], double* p_out)
 {
     double P[kGroup], k[kGroup];
     bool edge[kGroup];
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
-        P[j] = (MODE != kHist) ? event_prob<MIXED>(sc, tab, pc.kA, pc.kL, ev[j].e, ev[j].f)
-                               : ev[j].e;
+        P[j] = (MODE != kHist) ? prob(ev[j].e, ev[j].f) : ev[j].e;
         k[j] = (MODE != kReweight) ? bin_floor_fast(ev[j].x, bc, edge[j]) : 0.0;
     }
     if (WRITE_P) {
@@ -388,10 +497,9 @@ __device__ __forceinline__ void tile_group(const SetConsts& sc, const Chan* tab,
 
 // The kLaneEvents events of one lane, fully unrolled: the loads of group
 // g + 1 are issued before group g is computed.
-template <int MODE, bool WRITE_P, bool FULL, bool MIXED>
-__device__ __forceinline__ void tile_events(const SetConsts& sc, const Chan* tab,
-                                            const PathConsts& pc, const BinConsts& bc,
-                                            double* hist, int lane, int64_t base, int64_t n,
+template <int MODE, bool WRITE_P, bool FULL, class PROB>
+__device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
+                                            int lane, int64_t base, int64_t n,
                                             const double* e_true, const uint8_t* flags,
                                             const double* weight, const double* e_reco,
                                             const double* value, double* p_out)
@@ -411,9 +519,9 @@ __device__ __forceinline__ void tile_events(const SetConsts& sc, const Chan* tab
                     base + int64_t((g + 1) * kGroup + j) * kTileLanes, n, e_true, flags, weight,
                     e_reco, value);
         }
-        tile_group<MODE, WRITE_P, FULL, MIXED>(sc, tab, pc, bc, hist, lane,
-                                               base + int64_t(g * kGroup) * kTileLanes, n,
-                                               ev[g], p_out);
+        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane,
+                                        base + int64_t(g * kGroup) * kTileLanes, n, ev[g],
+                                        p_out);
     }
 }
 

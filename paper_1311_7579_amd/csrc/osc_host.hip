@@ -291,7 +291,7 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
                     const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
                     const double* e_true, const uint8_t* flags, const double* weight,
                     const double* e_reco, const double* value, double* p_out,
-                    double* hist_out, hipStream_t stream)
+                    double* hist_out, hipStream_t stream, const osc::LayerPath* lp = nullptr)
 {
     const int nbt = bc.nb + 2;
     const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
@@ -301,8 +301,10 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
     if (st != OSC_OK) return st;
     double* scratch = static_cast<double*>(s->ptr);
     ProfRec* pr = prof_begin(ctx, stream);
-    hipError_t e = osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags, weight,
-                                     e_reco, value, p_out, scratch, stream);
+    hipError_t e = lp ? osc::launch_layered_tiles(mode, write_p, sc, *lp, bc, n, e_true, flags,
+                                                  weight, e_reco, p_out, scratch, stream)
+                      : osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags,
+                                          weight, e_reco, value, p_out, scratch, stream);
     if (pr) prof_mark(pr->mid, stream);
     if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
     if (pr) prof_mark(pr->end, stream);
@@ -424,6 +426,74 @@ osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                     path_consts(sample),
                     bin_consts(binning), sample->n, sample->e_true, sample->flags, sample->weight,
                     sample->e_reco, nullptr, p_out, hist_out, static_cast<hipStream_t>(stream));
+}
+
+namespace {
+
+// Layers of a piecewise-constant path: 1..kMaxLayers layers, each with
+// L >= 0, rho >= 0 (finite) and 0 <= Ye <= 1.
+bool layers_ok(const osc_layer* layers, int32_t n_layers)
+{
+    if (!layers || n_layers < 1 || n_layers > osc::kMaxLayers) return false;
+    for (int32_t j = 0; j < n_layers; ++j) {
+        const osc_layer& l = layers[j];
+        if (!is_finite(l.L_km) || l.L_km < 0.0 || !is_finite(l.rho_gcc) || l.rho_gcc < 0.0 ||
+            !is_finite(l.Ye) || l.Ye < 0.0 || l.Ye > 1.0)
+            return false;
+    }
+    return true;
+}
+
+osc::LayerPath layer_path(const osc_layer* layers, int32_t n_layers)
+{
+    osc::LayerPath lp{};
+    lp.n = n_layers;
+    for (int32_t j = 0; j < n_layers; ++j)
+        lp.layer[j] = osc::PathConsts{matter_constant() * layers[j].Ye * layers[j].rho_gcc,
+                                      phase_constant() * layers[j].L_km};
+    return lp;
+}
+
+}  // namespace
+
+osc_status osc_reweight_layered(osc_ctx* ctx, const osc_sample* sample, const osc_layer* layers,
+                                int32_t n_layers, int32_t set, double* p_out, void* stream)
+{
+    if (!ctx || !sample_ok(sample, false) || !layers_ok(layers, n_layers))
+        return OSC_ERR_INVALID_ARG;
+    if (sample->n > 0 && !p_out) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const osc::BinConsts bc{0.0, 1.0, 1.0, 1.0, 1};
+    const hipStream_t hs = static_cast<hipStream_t>(stream);
+    ProfRec* pr = prof_begin(ctx, hs);
+    const hipError_t e = osc::launch_layered_tiles(
+        0, true, ctx->consts[size_t(set)], layer_path(layers, n_layers), bc, sample->n,
+        sample->e_true, sample->flags, nullptr, nullptr, p_out, nullptr, hs);
+    if (pr) {
+        prof_mark(pr->mid, hs);
+        (void)hipEventDestroy(pr->end);
+        pr->end = nullptr;
+    }
+    return device_status(e);
+}
+
+osc_status osc_fill_pdf_layered(osc_ctx* ctx, const osc_sample* sample, const osc_layer* layers,
+                                int32_t n_layers, int32_t set, const osc_binning* binning,
+                                double* hist_out, double* p_out, void* stream)
+{
+    if (!ctx || !sample_ok(sample, true) || !hist_out || !layers_ok(layers, n_layers))
+        return OSC_ERR_INVALID_ARG;
+    if (!binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const osc::LayerPath lp = layer_path(layers, n_layers);
+    return run_hist(ctx, 1, p_out != nullptr, false, ctx->consts[size_t(set)], osc::PathConsts{},
+                    bin_consts(binning), sample->n, sample->e_true, sample->flags,
+                    sample->weight, sample->e_reco, nullptr, p_out, hist_out,
+                    static_cast<hipStream_t>(stream), &lp);
 }
 
 osc_status osc_fill_hist(osc_ctx* ctx, int64_t n, const double* value, const double* weight,

@@ -32,6 +32,7 @@ constexpr int kLaneShare = kTileLanes / kHistLanes;
 #endif
 constexpr int kTileWavesPerSimd = OSC_TILE_WAVES;
 constexpr int kBatchWavesPerSimd = 4;
+constexpr int kLayeredWavesPerSimd = 3;
 
 // Largest event count accepted.
 constexpr int64_t kMaxEvents = int64_t(1) << 32;
@@ -99,6 +100,14 @@ struct SetConsts {
 struct PathConsts {
     double kA;   // matter term per GeV: A = +-kA * E (eV^2)
     double kL;   // phase per eV^2 per 1/GeV: phase = kL * lambda / E
+};
+
+// A path of piecewise-constant density: layers in the order the neutrino
+// crosses them, each with its own PathConsts.
+constexpr int kMaxLayers = 32;
+struct LayerPath {
+    int32_t n;
+    PathConsts layer[kMaxLayers];
 };
 
 struct BinConsts {

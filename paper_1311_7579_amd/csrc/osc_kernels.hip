@@ -44,12 +44,47 @@ void tile_kernel(
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
+    const ConstDensityProb<MIXED> prob{&sc, tab, pc.kA, pc.kL};
     if ((tile + 1) * kTileEvents <= n)
-        tile_events<MODE, WRITE_P, true, MIXED>(sc, tab, pc, bc, hist, lane, base, n, e_true,
-                                                flags, weight, e_reco, value, p_out);
+        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
+                                         e_reco, value, p_out);
     else
-        tile_events<MODE, WRITE_P, false, MIXED>(sc, tab, pc, bc, hist, lane, base, n, e_true,
-                                                 flags, weight, e_reco, value, p_out);
+        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, base, n, e_true, flags, weight,
+                                          e_reco, value, p_out);
+
+    if (MODE != kReweight) {
+        __syncthreads();
+        tile_write(hist, lane, nbt, tile, partial);
+    }
+}
+
+// The same tile body with P through a layered path (FP64 only).
+template <int MODE, bool WRITE_P>
+__global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kLayeredWavesPerSimd)))
+void layered_tile_kernel(SetConsts sc, LayerPath lp, BinConsts bc, int64_t n,
+                         const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
+                         const double* __restrict__ weight, const double* __restrict__ e_reco,
+                         double* __restrict__ p_out, double* __restrict__ partial)
+{
+    extern __shared__ double hist[];
+    __shared__ Chan tab[kChannels];
+
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t base = tile * kTileEvents + lane;
+    const int nbt = bc.nb + 2;
+
+    load_tab(sc, tab, lane);
+    if (MODE != kReweight) hist_zero(hist, lane, nbt);
+    __syncthreads();
+
+    const LayeredProb prob{&sc, tab, &lp};
+    if ((tile + 1) * kTileEvents <= n)
+        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
+                                         e_reco, nullptr, p_out);
+    else
+        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, base, n, e_true, flags, weight,
+                                          e_reco, nullptr, p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -125,6 +160,28 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
         OSC_LAUNCH(kHist, false, false);
     }
 #undef OSC_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
+                                const LayerPath& lp, const BinConsts& bc, int64_t n,
+                                const double* e_true, const uint8_t* flags, const double* weight,
+                                const double* e_reco, double* p_out, double* partial,
+                                hipStream_t stream)
+{
+    const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
+    if (ntiles == 0) return hipSuccess;
+    const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
+    const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
+    if (mode == kReweight)
+        hipLaunchKernelGGL((layered_tile_kernel<kReweight, true>), grid, block, lds, stream, sc, lp,
+                           bc, n, e_true, flags, weight, e_reco, p_out, partial);
+    else if (write_p)
+        hipLaunchKernelGGL((layered_tile_kernel<kPdf, true>), grid, block, lds, stream, sc, lp, bc,
+                           n, e_true, flags, weight, e_reco, p_out, partial);
+    else
+        hipLaunchKernelGGL((layered_tile_kernel<kPdf, false>), grid, block, lds, stream, sc, lp,
+                           bc, n, e_true, flags, weight, e_reco, p_out, partial);
     return hipGetLastError();
 }
 
@@ -213,6 +270,8 @@ hipError_t set_kernel_attributes(size_t max_dyn_lds)
         reinterpret_cast<const void*>(&tile_kernel<kPdf, true, true>),
         reinterpret_cast<const void*>(&tile_kernel<kPdf, false, true>),
         reinterpret_cast<const void*>(&tile_kernel<kHist, false, false>),
+        reinterpret_cast<const void*>(&layered_tile_kernel<kPdf, true>),
+        reinterpret_cast<const void*>(&layered_tile_kernel<kPdf, false>),
     };
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -18,6 +18,13 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const double* e_reco, const double* value, double* p_out,
                         double* partial, hipStream_t stream);
 
+// launch_tiles with P through a layered path (FP64; mode 0 or 1).
+hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
+                                const LayerPath& lp, const BinConsts& bc, int64_t n,
+                                const double* e_true, const uint8_t* flags, const double* weight,
+                                const double* e_reco, double* p_out, double* partial,
+                                hipStream_t stream);
+
 // The levels of the histogram merge for n_samples samples of tiles[s]
 // tiles each (per parameter set), and the scratch strides they need.
 struct MergePlan {

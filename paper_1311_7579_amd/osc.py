@@ -47,6 +47,16 @@ class osc_binning(ctypes.Structure):
                 ("e_scale", ctypes.c_double)]
 
 
+class osc_layer(ctypes.Structure):
+    _fields_ = [("L_km", ctypes.c_double), ("rho_gcc", ctypes.c_double), ("Ye", ctypes.c_double)]
+
+
+def layers_array(layers):
+    """(L_km, rho_gcc, Ye) triples (or osc_layer) -> ctypes array."""
+    items = [l if isinstance(l, osc_layer) else osc_layer(*map(float, l)) for l in layers]
+    return (osc_layer * len(items))(*items)
+
+
 class osc_batch_config(ctypes.Structure):
     _fields_ = [("sets_per_item", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
@@ -122,6 +132,12 @@ def load():
     L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                    ctypes.c_int, i32, ctypes.POINTER(vp)]
     L.osc_batch_create.restype = st
+    L.osc_reweight_layered.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_layer),
+                                       i32, i32, vp, vp]
+    L.osc_reweight_layered.restype = st
+    L.osc_fill_pdf_layered.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_layer),
+                                       i32, i32, ctypes.POINTER(osc_binning), vp, vp, vp]
+    L.osc_fill_pdf_layered.restype = st
     L.osc_template_create.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_binning),
                                       ctypes.POINTER(osc_binning), ctypes.POINTER(vp),
                                       ctypes.POINTER(i64)]
@@ -297,6 +313,22 @@ class Context:
         _check(load().osc_fill_pdf(self.handle, ctypes.byref(cs), int(set_index), ctypes.byref(b),
                                    int(precision), _ptr(hist_out), _ptr(p_out), _stream(stream)),
                "osc_fill_pdf")
+
+    def osc_reweight_layered(self, sample: DeviceSample, layers, set_index, p_out, stream=None):
+        cs = sample.c_struct()
+        arr = layers_array(layers)
+        _check(load().osc_reweight_layered(self.handle, ctypes.byref(cs), arr, len(arr),
+                                           int(set_index), _ptr(p_out), _stream(stream)),
+               "osc_reweight_layered")
+
+    def osc_fill_pdf_layered(self, sample: DeviceSample, layers, set_index, nbins, lo, hi,
+                             hist_out, p_out=None, stream=None, e_scale=0.0):
+        cs = sample.c_struct()
+        arr = layers_array(layers)
+        b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
+        _check(load().osc_fill_pdf_layered(self.handle, ctypes.byref(cs), arr, len(arr),
+                                           int(set_index), ctypes.byref(b), _ptr(hist_out),
+                                           _ptr(p_out), _stream(stream)), "osc_fill_pdf_layered")
 
     def osc_profile_enable(self, on=True):
         _check(load().osc_profile_enable(self.handle, int(bool(on))), "osc_profile_enable")
