@@ -45,15 +45,16 @@ FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # HBM traffic of one launch of the fused kernel on this workload, read with
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and scaled by
 # what the same counters read for a plain device copy of known size.  Valid
-# only for the kernel sources it was taken on (sha256 over KERNEL_SOURCES);
-# reported as null once they change.
+# only for the kernel sources and build flags it was taken on (sha256 over
+# KERNEL_SOURCES); reported as null once they change.
 KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_internal.h",
-                  "paper_1311_7579_amd/csrc/osc_kernels.hip")
+                  "paper_1311_7579_amd/csrc/osc_kernels.hip",
+                  "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122518.8, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 94071.3, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
-    "source_sha256": "2c1fe0488a0e3524faaa9c565ce43511ecbaac23b83a6afed80bb5d19ee5522a",
+    "fetch_kib": 122508.6, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 94116.2, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "source_sha256": "8957e00194ba764c9342a72eed50b050a01fcee59407c535fbefd7300fb2c3f0",
 }
 
 
@@ -345,9 +346,46 @@ def serving_form(osc, ctx, n_requests):
             summ.update({k2: st[k2] for k2 in ("max_in_flight", "max_queued", "budget_waits",
                                                "peak_scratch_bytes", "completed")})
             out[f"rate_{frac}"] = summ
+        out["mcmc"] = serving_mcmc(osc, ctx, server, ds)
     finally:
         server.close()
     return out
+
+
+def serving_mcmc(osc, ctx, server, ds, n_chains=8, n_steps=250):
+    """Sec. 2.2's fit as served requests: fake data drawn (Poisson, seed 81)
+    from every sample's PDF at Table 1, scaled to 3000 expected events in
+    the 1e6-event sample's regular bins; 8 Metropolis chains over
+    (sin^2 theta23, dm2_32) on that sample, FP64, each proposal one request
+    whose -2 ln L (Eq. 2) is computed on the device."""
+    import numpy as np
+    import torch
+    from paper_1311_7579_amd import serving, workload
+    truth = workload.TABLE1
+    ctx.osc_set_params([truth])
+    h = torch.empty((len(ds), NBINS + 2), dtype=torch.float64, device="cuda")
+    for k, d in enumerate(ds):
+        ctx.osc_fill_pdf(d, 0, NBINS, LO, HI, h[k])
+    pdf = h.cpu().numpy()[:, :NBINS]
+    target = int(np.argmin([abs(d.n - 1_000_000) for d in ds]))
+    mu_scale = 3000.0 / pdf[target].sum()
+    data = np.random.default_rng(81).poisson(mu_scale * pdf).astype(float)
+    server.set_data(data, mu_scale)
+    try:
+        r = serving.run_mcmc(server, start=dict(truth, sin2_th23=0.43, dm2_32=2.3e-3),
+                             free=("sin2_th23", "dm2_32"), sigmas=(0.015, 2.5e-5),
+                             bounds=((0.3, 0.7), (2.0e-3, 2.8e-3)), n_chains=n_chains,
+                             n_steps=n_steps, seed=82, sample=target, tier=osc.OSC_FP64)
+    finally:
+        server.set_data(None)
+    tail = r["chains"][:, n_steps // 2:, :].reshape(-1, 2)
+    return {"config": f"{n_chains} chains x {n_steps} steps on the {ds[target].n}-event sample, "
+                      "3000 expected events, free (sin2_th23, dm2_32), Table 1 truth",
+            "acceptance": r["acceptance"], "steps_per_s": r["steps_per_s"],
+            "evals_per_s": r["steps_per_s"] * ds[target].n,
+            "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+            "posterior_second_half": {"sin2_th23": [float(tail[:, 0].mean()), float(tail[:, 0].std())],
+                                      "dm2_32": [float(tail[:, 1].mean()), float(tail[:, 1].std())]}}
 
 
 def main():
@@ -391,16 +429,6 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = N_EVENTS / (ms_per_step * 1e-3)
 
-    # per-kernel device time with hipEvents recorded on the launch stream
-    ctx.osc_profile_enable(True)
-    for _ in range(args.steps):
-        step()
-    ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
-    ctx.osc_profile_enable(False)
-    kernel_ms = ev_ms / max(ev_n, 1)
-    waves_per_cu = ctx.osc_occupancy(NBINS, True)
-    merge_avg_ms = merge_ms / max(merge_n, 1)
-
     # end-to-end latency of single calls: launch -> histogram on the host
     lat = []
     host_hist = torch.empty(NBINS + 2, dtype=torch.float64, pin_memory=True)
@@ -410,6 +438,17 @@ def main():
         host_hist.copy_(hist, non_blocking=False)
         lat.append(time.perf_counter() - a)
     lat = np.array(lat if lat else [float("nan")]) * 1e3
+    # per-kernel device time, after the latency calls have kept the GPU busy:
+    # the fused kernel's own dispatch records its begin and end in hipEvents
+    # on the launch stream
+    ctx.osc_profile_enable(True)
+    for _ in range(max(args.steps, 50)):
+        step()
+    ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
+    ctx.osc_profile_enable(False)
+    kernel_ms = ev_ms / max(ev_n, 1)
+    waves_per_cu = ctx.osc_occupancy(NBINS, True)
+    merge_avg_ms = merge_ms / max(merge_n, 1)
 
     # The fused kernel is bound by VALU issue (FP64 arithmetic), not by HBM:
     # roofline against the FP64 vector peak, HBM position alongside.

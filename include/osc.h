@@ -239,15 +239,18 @@ osc_status osc_fill_pdf_bincentre(osc_ctx* ctx, const osc_template* t, int32_t s
 
 /* Sec. 2.2, Eq. (2): the binned likelihood of the fitter, read as a
  * product over the regular bins of Poisson probabilities of observed counts
- * d_b given the PDF mu_b:  -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)
+ * d_b given the expectation mu_b = mu_scale * hist_b (mu_scale > 0: the
+ * exposure that turns the Monte Carlo PDF into expected counts):
+ *   -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + ln d_b!)
  * (a bin with mu_b = 0 adds 0 if d_b = 0, else +infinity; under/overflow
  * entries are not used).  hist: device, n_hist histograms of nbins + 2
  * entries (the layout of osc_fill_pdf / osc_batch_run); data: device,
  * n_data rows of nbins counts, histogram k compared with row k % n_data
  * (so batched histograms [set][sample] pair with per-sample data rows);
  * nll_out: device, n_hist values.  The sum over bins has a fixed order. */
-osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, const double* data,
-                           int64_t n_data, int32_t nbins, double* nll_out, void* stream);
+osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, double mu_scale,
+                           const double* data, int64_t n_data, int32_t nbins, double* nll_out,
+                           void* stream);
 
 /* ---- Batched form ---------------------------------------------------------
  * Every parameter set x every sample of a list in one persistent kernel
@@ -340,16 +343,25 @@ osc_status osc_server_destroy(osc_server* server);
 osc_status osc_server_submit(osc_server* server, const osc_params* set, int32_t sample,
                              osc_precision precision, uint64_t* ticket);
 
+/* Data for the fitter's likelihood (Sec. 2.2, Eq. 2): n_samples rows of
+ * nbins observed counts (host, copied) and the exposure mu_scale > 0.  Once
+ * set, every request admitted afterwards also computes, on the device
+ * after its histogram, -2 ln L of mu_scale * histogram against its
+ * sample's row (the reduction of osc_poisson_nll).  data = NULL clears
+ * them.  OSC_ERR_NOT_READY while requests are in flight. */
+osc_status osc_server_set_data(osc_server* server, const double* data, double mu_scale);
+
 /* Non-blocking: OSC_ERR_NOT_READY while the request runs; once done,
- * copies the histogram (nbins + 2 FP64, host memory; nullable), the latency
- * from submission to the histogram on the host and the time spent queued
+ * copies the histogram (nbins + 2 FP64, host memory; nullable), -2 ln L
+ * (nullable; NaN when the request ran without data), the latency from
+ * submission to the results on the host and the time spent queued
  * (seconds; nullable), forgets the ticket and returns the request's status. */
-osc_status osc_server_poll(osc_server* server, uint64_t ticket, double* hist, double* latency_s,
-                           double* queue_s);
+osc_status osc_server_poll(osc_server* server, uint64_t ticket, double* hist, double* nll,
+                           double* latency_s, double* queue_s);
 
 /* Blocking form of osc_server_poll. */
-osc_status osc_server_wait(osc_server* server, uint64_t ticket, double* hist, double* latency_s,
-                           double* queue_s);
+osc_status osc_server_wait(osc_server* server, uint64_t ticket, double* hist, double* nll,
+                           double* latency_s, double* queue_s);
 
 osc_status osc_server_get_stats(osc_server* server, osc_server_stats* out);
 

@@ -18,7 +18,10 @@ ARCH = os.environ.get("OSC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-ffp-contract=fast-honor-pragmas", "-Wall",
+    # FMA contraction only within one expression (and never where a
+    # "#pragma clang fp contract(off)" says so): every kernel instantiation
+    # then rounds the same arithmetic the same way
+    "-ffp-contract=on", "-Wall",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # interleave independent events within a wave (occupancy is bounded by
     # the LDS histograms, not by registers)

@@ -152,18 +152,17 @@ void drop_profile(osc_ctx* ctx)
     ctx->prof.clear();
 }
 
-// Starts a profiling record on `stream` when profiling is on.  The timing
-// events skip the system-scope fence (they only bracket kernels on one
-// device), which keeps their own cost out of the measured interval.
-ProfRec* prof_begin(osc_ctx* ctx, hipStream_t stream)
+// Starts a profiling record when profiling is on.  `start` and `mid` are
+// handed to the launch of the per-event kernel, which records its own
+// begin and end time in them (the dispatch's timestamps, so the interval
+// is the kernel's execution alone); `end` is recorded on the stream after
+// the merge.
+ProfRec* prof_begin(osc_ctx* ctx, hipStream_t)
 {
     if (!ctx->profiling) return nullptr;
     ProfRec r;
-    const unsigned fl = hipEventDisableSystemFence;
-    if (hipEventCreateWithFlags(&r.start, fl) != hipSuccess ||
-        hipEventCreateWithFlags(&r.mid, fl) != hipSuccess ||
-        hipEventCreateWithFlags(&r.end, fl) != hipSuccess ||
-        hipEventRecord(r.start, stream) != hipSuccess) {
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.mid) != hipSuccess ||
+        hipEventCreate(&r.end) != hipSuccess) {
         for (hipEvent_t e : {r.start, r.mid, r.end})
             if (e) (void)hipEventDestroy(e);
         return nullptr;
@@ -301,11 +300,11 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
     if (st != OSC_OK) return st;
     double* scratch = static_cast<double*>(s->ptr);
     ProfRec* pr = prof_begin(ctx, stream);
+    hipEvent_t t0 = pr ? pr->start : nullptr, t1 = pr ? pr->mid : nullptr;
     hipError_t e = lp ? osc::launch_layered_tiles(mode, write_p, sc, *lp, bc, n, e_true, flags,
-                                                  weight, e_reco, p_out, scratch, stream)
+                                                  weight, e_reco, p_out, scratch, stream, t0, t1)
                       : osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags,
-                                          weight, e_reco, value, p_out, scratch, stream);
-    if (pr) prof_mark(pr->mid, stream);
+                                          weight, e_reco, value, p_out, scratch, stream, t0, t1);
     if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
     if (pr) prof_mark(pr->end, stream);
     st = release_scratch(s, stream);
@@ -403,9 +402,9 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, dou
     const hipError_t e = osc::launch_tiles(0, true, false, ctx->consts[size_t(set)],
                                            path_consts(sample), bc,
                                            sample->n, sample->e_true, sample->flags, nullptr,
-                                           nullptr, nullptr, p_out, nullptr, hs);
+                                           nullptr, nullptr, p_out, nullptr, hs,
+                                           pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) {
-        prof_mark(pr->mid, hs);
         (void)hipEventDestroy(pr->end);
         pr->end = nullptr;
     }
@@ -470,9 +469,9 @@ osc_status osc_reweight_layered(osc_ctx* ctx, const osc_sample* sample, const os
     ProfRec* pr = prof_begin(ctx, hs);
     const hipError_t e = osc::launch_layered_tiles(
         0, true, ctx->consts[size_t(set)], layer_path(layers, n_layers), bc, sample->n,
-        sample->e_true, sample->flags, nullptr, nullptr, p_out, nullptr, hs);
+        sample->e_true, sample->flags, nullptr, nullptr, p_out, nullptr, hs,
+        pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) {
-        prof_mark(pr->mid, hs);
         (void)hipEventDestroy(pr->end);
         pr->end = nullptr;
     }
@@ -555,16 +554,18 @@ osc_status osc_profile_read(osc_ctx* ctx, double* event_kernel_ms, int64_t* even
     return st;
 }
 
-osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, const double* data,
-                           int64_t n_data, int32_t nbins, double* nll_out, void* stream)
+osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, double mu_scale,
+                           const double* data, int64_t n_data, int32_t nbins, double* nll_out,
+                           void* stream)
 {
     if (!ctx || n_hist < 0 || n_data < 1 || nbins < 1 || nbins > ctx->max_nbins)
         return OSC_ERR_INVALID_ARG;
+    if (!is_finite(mu_scale) || !(mu_scale > 0.0)) return OSC_ERR_INVALID_ARG;
     if (n_hist > 0 && (!hist || !data || !nll_out)) return OSC_ERR_INVALID_ARG;
     if (n_hist > int64_t(1) << 31) return OSC_ERR_INVALID_ARG;
     if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
-    return device_status(osc::launch_poisson_nll(hist, n_hist, data, n_data, nbins, nll_out,
-                                                 static_cast<hipStream_t>(stream)));
+    return device_status(osc::launch_poisson_nll(hist, n_hist, mu_scale, data, n_data, nbins,
+                                                 nll_out, static_cast<hipStream_t>(stream)));
 }
 
 void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events, int32_t* accumulators)

@@ -9,6 +9,8 @@
 // fixed binary tree; a merge kernel adds the tile results per bin in a
 // fixed binary tree.  No atomics: the bits of the histogram do not depend
 // on the launch shape.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <vector>
 
@@ -101,11 +103,12 @@ __global__ __launch_bounds__(kMergeThreads) void merge_level_kernel(MergeLevel L
 }
 
 // Eq. (2) as a product of Poisson probabilities over the regular bins:
-// -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + lgamma(d_b + 1)).  One wave per
-// histogram; lane l adds bins l, l + 64, ... in ascending order, then the
-// lanes meet in the wave's butterfly tree (a fixed order).
+// -2 ln L = 2 sum_b (mu_b - d_b ln mu_b + lgamma(d_b + 1)), mu_b = scale *
+// hist_b.  One wave per histogram; lane l adds bins l, l + 64, ... in
+// ascending order, then the lanes meet in the wave's butterfly tree (a
+// fixed order).
 __global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restrict__ hist,
-                                                         int64_t n_data,
+                                                         double scale, int64_t n_data,
                                                          const double* __restrict__ data,
                                                          int nbins, double* __restrict__ out)
 {
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restric
     const double* d = data + (k % n_data) * nbins;
     double acc = 0.0;
     for (int b = lane; b < nbins; b += 64) {
-        const double m = mu[b], x = d[b];
+        const double m = scale * mu[b], x = d[b];
         const double term = m == 0.0 ? (x == 0.0 ? 0.0 : __builtin_inf())
                                      : m - x * log(m) + lgamma(x + 1.0);
         acc = acc + term;
@@ -126,12 +129,13 @@ __global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restric
 
 }  // namespace
 
-hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, const double* data,
-                              int64_t n_data, int nbins, double* out, hipStream_t stream)
+hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
+                              const double* data, int64_t n_data, int nbins, double* out,
+                              hipStream_t stream)
 {
     if (n_hist == 0) return hipSuccess;
     hipLaunchKernelGGL(poisson_nll_kernel, dim3(unsigned(n_hist)), dim3(64), 0, stream, hist,
-                       n_data, data, nbins, out);
+                       scale, n_data, data, nbins, out);
     return hipGetLastError();
 }
 
@@ -139,15 +143,17 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const PathConsts& pc, const BinConsts& bc, int64_t n,
                         const double* e_true, const uint8_t* flags, const double* weight,
                         const double* e_reco, const double* value, double* p_out,
-                        double* partial, hipStream_t stream)
+                        double* partial, hipStream_t stream, hipEvent_t ev_begin,
+                        hipEvent_t ev_end)
 {
     const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
     if (ntiles == 0) return hipSuccess;
     const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
     const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
 #define OSC_LAUNCH(M, W, X)                                                                      \
-    hipLaunchKernelGGL((tile_kernel<M, W, X>), grid, block, lds, stream, sc, pc, bc, n, ntiles,  \
-                       e_true, flags, weight, e_reco, value, p_out, partial)
+    hipExtLaunchKernelGGL((tile_kernel<M, W, X>), grid, block, lds, stream, ev_begin, ev_end, 0,  \
+                          sc, pc, bc, n, ntiles, e_true, flags, weight, e_reco, value, p_out,     \
+                          partial)
     if (mode == kReweight) {
         if (mixed) OSC_LAUNCH(kReweight, true, true);
         else OSC_LAUNCH(kReweight, true, false);
@@ -167,21 +173,24 @@ hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
                                 const LayerPath& lp, const BinConsts& bc, int64_t n,
                                 const double* e_true, const uint8_t* flags, const double* weight,
                                 const double* e_reco, double* p_out, double* partial,
-                                hipStream_t stream)
+                                hipStream_t stream, hipEvent_t ev_begin, hipEvent_t ev_end)
 {
     const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
     if (ntiles == 0) return hipSuccess;
     const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
     const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
     if (mode == kReweight)
-        hipLaunchKernelGGL((layered_tile_kernel<kReweight, true>), grid, block, lds, stream, sc, lp,
-                           bc, n, e_true, flags, weight, e_reco, p_out, partial);
+        hipExtLaunchKernelGGL((layered_tile_kernel<kReweight, true>), grid, block, lds, stream,
+                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
+                              p_out, partial);
     else if (write_p)
-        hipLaunchKernelGGL((layered_tile_kernel<kPdf, true>), grid, block, lds, stream, sc, lp, bc,
-                           n, e_true, flags, weight, e_reco, p_out, partial);
+        hipExtLaunchKernelGGL((layered_tile_kernel<kPdf, true>), grid, block, lds, stream,
+                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
+                              p_out, partial);
     else
-        hipLaunchKernelGGL((layered_tile_kernel<kPdf, false>), grid, block, lds, stream, sc, lp,
-                           bc, n, e_true, flags, weight, e_reco, p_out, partial);
+        hipExtLaunchKernelGGL((layered_tile_kernel<kPdf, false>), grid, block, lds, stream,
+                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
+                              p_out, partial);
     return hipGetLastError();
 }
 

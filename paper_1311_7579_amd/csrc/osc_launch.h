@@ -11,19 +11,22 @@ namespace osc {
 // 2 = histogram partials of given values.  partial holds ntiles x
 // (nbins + 2) FP64 entries, tile-major.
 // mixed selects the FP32-mixed tier (FP64 eigenvalues and phases, FP32
-// sine/cosine and amplitude assembly).
+// sine/cosine and amplitude assembly).  ev_begin / ev_end (optional,
+// created by the caller) receive the kernel's own begin and end times.
 hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const PathConsts& pc, const BinConsts& bc, int64_t n,
                         const double* e_true, const uint8_t* flags, const double* weight,
                         const double* e_reco, const double* value, double* p_out,
-                        double* partial, hipStream_t stream);
+                        double* partial, hipStream_t stream, hipEvent_t ev_begin = nullptr,
+                        hipEvent_t ev_end = nullptr);
 
 // launch_tiles with P through a layered path (FP64; mode 0 or 1).
 hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
                                 const LayerPath& lp, const BinConsts& bc, int64_t n,
                                 const double* e_true, const uint8_t* flags, const double* weight,
                                 const double* e_reco, double* p_out, double* partial,
-                                hipStream_t stream);
+                                hipStream_t stream, hipEvent_t ev_begin = nullptr,
+                                hipEvent_t ev_end = nullptr);
 
 // The levels of the histogram merge for n_samples samples of tiles[s]
 // tiles each (per parameter set), and the scratch strides they need.
@@ -45,11 +48,12 @@ size_t merge_scratch_bytes(const MergePlan& p, int64_t n_sets);
 hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, double* hist_out,
                         hipStream_t stream);
 
-// -2 ln L (Eq. 2, Poisson per regular bin) of n_hist histograms
-// (nbins + 2 entries each) against data rows (nbins entries; histogram k
-// uses row k % n_data).
-hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, const double* data,
-                              int64_t n_data, int nbins, double* out, hipStream_t stream);
+// -2 ln L (Eq. 2, Poisson per regular bin, mu = scale * hist) of n_hist
+// histograms (nbins + 2 entries each) against data rows (nbins entries;
+// histogram k uses row k % n_data).
+hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
+                              const double* data, int64_t n_data, int nbins, double* out,
+                              hipStream_t stream);
 
 // Resident one-wave blocks per CU of the per-event kernel of `mode` for
 // histograms of nbins bins.

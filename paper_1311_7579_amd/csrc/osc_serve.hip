@@ -7,8 +7,10 @@
 // device arena whose size is the memory budget; admitted requests run
 // concurrently on their streams and overlap on the device.  Each request
 // reduces its histogram privately in the fixed order of osc_fill_pdf, so its
-// result is the same alone and in any mix.  Completion is signalled by a
-// host function enqueued after the device-to-host copy of the histogram.
+// result is the same alone and in any mix.  When data rows are set, each
+// request also computes -2 ln L (Eq. 2) of its histogram against its
+// sample's row on the device.  Completion is signalled by a host function
+// enqueued after the device-to-host copy of the histogram (and -2 ln L).
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -20,9 +22,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include <cmath>
+
 #include "../../include/osc.h"
 #include "osc_host_common.h"
 #include "osc_internal.h"
+#include "osc_launch.h"
 
 namespace {
 
@@ -40,14 +45,16 @@ struct Request {
     osc_precision precision = OSC_FP64;
     double t_submit = 0.0, t_admit = 0.0, t_done = 0.0;
     bool done = false;
+    bool with_nll = false;
     osc_status status = OSC_OK;
     std::vector<double> hist;
+    double nll = NAN;
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
-    double* d_hist = nullptr;
-    double* h_hist = nullptr;   // pinned
+    double* d_hist = nullptr;   // nbins + 2 histogram entries, then -2 ln L
+    double* h_hist = nullptr;   // pinned, same layout
     bool busy = false;
     uint64_t ticket = 0;
     size_t off = 0, bytes = 0;
@@ -113,6 +120,9 @@ struct osc_server {
     std::vector<size_t> need;   // scratch bytes per sample
     osc_binning binning{};
     int nbt = 0;
+    double* d_data = nullptr;   // n_samples rows of nbins counts
+    double mu_scale = 1.0;
+    bool has_data = false;
     osc_server_config cfg{};
     char* arena_mem = nullptr;
     Arena arena;
@@ -148,7 +158,14 @@ osc_status launch(osc_server* sv, Slot& slot, Request& r)
                                 r.precision == OSC_FP32_MIXED, scratch, slot.d_hist, nullptr,
                                 slot.stream) != hipSuccess)
         return OSC_ERR_DEVICE;
-    if (hipMemcpyAsync(slot.h_hist, slot.d_hist, size_t(sv->nbt) * sizeof(double),
+    r.with_nll = sv->has_data;
+    const int nb = sv->binning.nbins;
+    if (r.with_nll &&
+        osc::launch_poisson_nll(slot.d_hist, 1, sv->mu_scale, sv->d_data + size_t(r.sample) * nb,
+                                1, nb, slot.d_hist + sv->nbt, slot.stream) != hipSuccess)
+        return OSC_ERR_DEVICE;
+    if (hipMemcpyAsync(slot.h_hist, slot.d_hist,
+                       size_t(sv->nbt + (r.with_nll ? 1 : 0)) * sizeof(double),
                        hipMemcpyDeviceToHost, slot.stream) != hipSuccess)
         return OSC_ERR_DEVICE;
     if (hipLaunchHostFunc(slot.stream, on_slot_done, &slot) != hipSuccess) return OSC_ERR_DEVICE;
@@ -165,6 +182,7 @@ void dispatch_loop(osc_server* sv)
             if (!slot.busy || !slot.finished.load(std::memory_order_acquire)) continue;
             Request& r = sv->reqs[slot.ticket];
             r.hist.assign(slot.h_hist, slot.h_hist + sv->nbt);
+            if (r.with_nll) r.nll = slot.h_hist[sv->nbt];
             r.t_done = slot.t_done.load(std::memory_order_relaxed);
             r.done = true;
             sv->arena.release(slot.off, slot.bytes);
@@ -238,6 +256,7 @@ void destroy_server(osc_server* sv)
         if (slot.h_hist) (void)hipHostFree(slot.h_hist);
     }
     if (sv->arena_mem) (void)hipFree(sv->arena_mem);
+    if (sv->d_data) (void)hipFree(sv->d_data);
     delete sv;
 }
 
@@ -275,9 +294,9 @@ osc_status osc_server_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_
     bool ok = budget > 0 && hipMalloc(&sv->arena_mem, budget) == hipSuccess;
     for (Slot& slot : sv->slots) {
         ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess &&
-             hipMalloc(&slot.d_hist, size_t(sv->nbt) * sizeof(double)) == hipSuccess &&
-             hipHostMalloc(&slot.h_hist, size_t(sv->nbt) * sizeof(double), hipHostMallocDefault) ==
-                 hipSuccess;
+             hipMalloc(&slot.d_hist, size_t(sv->nbt + 1) * sizeof(double)) == hipSuccess &&
+             hipHostMalloc(&slot.h_hist, size_t(sv->nbt + 1) * sizeof(double),
+                           hipHostMallocDefault) == hipSuccess;
     }
     if (!ok) {
         destroy_server(sv);
@@ -338,32 +357,53 @@ osc_status osc_server_submit(osc_server* sv, const osc_params* set, int32_t samp
     return OSC_OK;
 }
 
-static osc_status take_result(osc_server* sv, uint64_t ticket, double* hist, double* latency_s,
-                              double* queue_s)
+osc_status osc_server_set_data(osc_server* sv, const double* data, double mu_scale)
+{
+    if (!sv) return OSC_ERR_INVALID_ARG;
+    if (data && (!std::isfinite(mu_scale) || !(mu_scale > 0.0))) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->stats.in_flight > 0) return OSC_ERR_NOT_READY;
+    if (!data) {
+        sv->has_data = false;
+        return OSC_OK;
+    }
+    const size_t bytes = sv->samples.size() * size_t(sv->binning.nbins) * sizeof(double);
+    if (hipSetDevice(sv->device) != hipSuccess) return OSC_ERR_DEVICE;
+    if (!sv->d_data && hipMalloc(&sv->d_data, bytes) != hipSuccess) return OSC_ERR_OUT_OF_MEMORY;
+    if (hipMemcpy(sv->d_data, data, bytes, hipMemcpyHostToDevice) != hipSuccess)
+        return OSC_ERR_DEVICE;
+    sv->mu_scale = mu_scale;
+    sv->has_data = true;
+    return OSC_OK;
+}
+
+static osc_status take_result(osc_server* sv, uint64_t ticket, double* hist, double* nll,
+                              double* latency_s, double* queue_s)
 {
     auto it = sv->reqs.find(ticket);
     Request& r = it->second;
     const osc_status st = r.status;
     if (st == OSC_OK && hist) std::copy(r.hist.begin(), r.hist.end(), hist);
+    if (nll) *nll = (st == OSC_OK) ? r.nll : NAN;
     if (latency_s) *latency_s = r.t_done - r.t_submit;
     if (queue_s) *queue_s = r.t_admit - r.t_submit;
     sv->reqs.erase(it);
     return st;
 }
 
-osc_status osc_server_poll(osc_server* sv, uint64_t ticket, double* hist, double* latency_s,
-                           double* queue_s)
+osc_status osc_server_poll(osc_server* sv, uint64_t ticket, double* hist, double* nll,
+                           double* latency_s, double* queue_s)
 {
     if (!sv) return OSC_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lock(sv->mu);
     auto it = sv->reqs.find(ticket);
     if (it == sv->reqs.end()) return OSC_ERR_INVALID_ARG;
     if (!it->second.done) return OSC_ERR_NOT_READY;
-    return take_result(sv, ticket, hist, latency_s, queue_s);
+    return take_result(sv, ticket, hist, nll, latency_s, queue_s);
 }
 
-osc_status osc_server_wait(osc_server* sv, uint64_t ticket, double* hist, double* latency_s,
-                           double* queue_s)
+osc_status osc_server_wait(osc_server* sv, uint64_t ticket, double* hist, double* nll,
+                           double* latency_s, double* queue_s)
 {
     if (!sv) return OSC_ERR_INVALID_ARG;
     std::unique_lock<std::mutex> lock(sv->mu);
@@ -374,7 +414,7 @@ osc_status osc_server_wait(osc_server* sv, uint64_t ticket, double* hist, double
         return j == sv->reqs.end() || j->second.done;
     });
     if (sv->reqs.find(ticket) == sv->reqs.end()) return OSC_ERR_INVALID_ARG;
-    return take_result(sv, ticket, hist, latency_s, queue_s);
+    return take_result(sv, ticket, hist, nll, latency_s, queue_s);
 }
 
 osc_status osc_server_get_stats(osc_server* sv, osc_server_stats* out)

@@ -10,6 +10,7 @@ the stream is torch's current stream unless one is given.
 import ctypes
 import os
 from dataclasses import dataclass
+from typing import NamedTuple
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libosc.so")
@@ -127,7 +128,7 @@ def load():
     L.osc_occupancy.restype = st
     L.osc_max_nbins.argtypes = [vp]
     L.osc_max_nbins.restype = i32
-    L.osc_poisson_nll.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+    L.osc_poisson_nll.argtypes = [vp, vp, i64, ctypes.c_double, vp, i64, i32, vp, vp]
     L.osc_poisson_nll.restype = st
     L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                    ctypes.c_int, i32, ctypes.POINTER(vp)]
@@ -170,8 +171,10 @@ def load():
     for name in ("osc_server_poll", "osc_server_wait"):
         fn = getattr(L, name)
         fn.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(ctypes.c_double),
-                       ctypes.POINTER(ctypes.c_double)]
+                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         fn.restype = st
+    L.osc_server_set_data.argtypes = [vp, vp, ctypes.c_double]
+    L.osc_server_set_data.restype = st
     L.osc_server_get_stats.argtypes = [vp, ctypes.POINTER(osc_server_stats)]
     L.osc_server_get_stats.restype = st
     L.osc_server_request_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
@@ -342,14 +345,16 @@ class Context:
                                        ctypes.byref(c), ctypes.byref(d)), "osc_profile_read")
         return a.value, b.value, c.value, d.value
 
-    def osc_poisson_nll(self, hist, data, nll_out, stream=None):
-        """-2 ln L of every histogram in `hist` (..., nbins + 2) against the
-        rows of `data` (n_data, nbins); histogram k uses row k % n_data."""
+    def osc_poisson_nll(self, hist, data, nll_out, stream=None, mu_scale=1.0):
+        """-2 ln L of every histogram in `hist` (..., nbins + 2), scaled by
+        mu_scale, against the rows of `data` (n_data, nbins); histogram k
+        uses row k % n_data."""
         nbins = int(data.shape[-1])
         n_hist = int(hist.numel() // (nbins + 2))
         n_data = int(data.numel() // nbins)
-        _check(load().osc_poisson_nll(self.handle, _ptr(hist), n_hist, _ptr(data), n_data, nbins,
-                                      _ptr(nll_out), _stream(stream)), "osc_poisson_nll")
+        _check(load().osc_poisson_nll(self.handle, _ptr(hist), n_hist, float(mu_scale), _ptr(data),
+                                      n_data, nbins, _ptr(nll_out), _stream(stream)),
+               "osc_poisson_nll")
 
     def osc_fill_hist(self, value, weight, e_reco, nbins, lo, hi, hist_out, stream=None,
                       e_scale=0.0):
@@ -473,6 +478,13 @@ class Batch:
         return ms.value
 
 
+class ServerResult(NamedTuple):
+    hist: object        # numpy, nbins + 2
+    latency_s: float
+    queue_s: float
+    nll: float          # -2 ln L, NaN when the server has no data
+
+
 class Server:
     """osc_server: FIFO request loop with slot- and memory-bound admission.
 
@@ -509,26 +521,41 @@ class Server:
                                         ctypes.byref(t)), "osc_server_submit")
         return t.value
 
+    def set_data(self, data, mu_scale=1.0):
+        """Observed counts, one row of nbins per sample (or None to clear):
+        requests admitted afterwards also return -2 ln L of mu_scale * hist
+        against their sample's row."""
+        import numpy as np
+        if data is None:
+            _check(load().osc_server_set_data(self.handle, None, float(mu_scale)),
+                   "osc_server_set_data")
+            return
+        d = np.ascontiguousarray(data, dtype=np.float64)
+        if d.shape != (len(self.samples), self.nbins):
+            raise ValueError("data must have one row of nbins counts per sample")
+        _check(load().osc_server_set_data(self.handle, ctypes.c_void_p(d.ctypes.data),
+                                          float(mu_scale)), "osc_server_set_data")
+
     def _result(self, fn, ticket):
         import numpy as np
         h = np.empty(self.nbins + 2, dtype=np.float64)
-        lat, q = ctypes.c_double(), ctypes.c_double()
+        nll, lat, q = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         st = fn(self.handle, ctypes.c_uint64(ticket), ctypes.c_void_p(h.ctypes.data),
-                ctypes.byref(lat), ctypes.byref(q))
-        return st, h, lat.value, q.value
+                ctypes.byref(nll), ctypes.byref(lat), ctypes.byref(q))
+        return st, ServerResult(h, lat.value, q.value, nll.value)
 
     def poll(self, ticket):
-        """(hist, latency_s, queue_s) once done, else None."""
-        st, h, lat, q = self._result(load().osc_server_poll, ticket)
+        """ServerResult(hist, latency_s, queue_s, nll) once done, else None."""
+        st, r = self._result(load().osc_server_poll, ticket)
         if st == OSC_ERR_NOT_READY:
             return None
         _check(st, "osc_server_poll")
-        return h, lat, q
+        return r
 
     def wait(self, ticket):
-        st, h, lat, q = self._result(load().osc_server_wait, ticket)
+        st, r = self._result(load().osc_server_wait, ticket)
         _check(st, "osc_server_wait")
-        return h, lat, q
+        return r
 
     def stats(self) -> dict:
         s = osc_server_stats()

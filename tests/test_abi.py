@@ -34,7 +34,10 @@ def test_header_declares_the_entry_points():
                  "osc_fill_hist", "osc_validate_params", "osc_reduction_layout",
                  "osc_max_nbins", "osc_status_string", "osc_occupancy", "osc_profile_enable",
                  "osc_profile_read", "osc_poisson_nll", "osc_batch_create", "osc_batch_run",
-                 "osc_batch_tune", "osc_server_create", "osc_server_submit", "osc_server_wait"):
+                 "osc_batch_tune", "osc_server_create", "osc_server_submit", "osc_server_wait",
+                 "osc_server_set_data", "osc_server_poll", "osc_reweight_layered",
+                 "osc_fill_pdf_layered", "osc_template_create", "osc_template_copy",
+                 "osc_template_destroy", "osc_fill_pdf_bincentre"):
         assert want in names
 
 

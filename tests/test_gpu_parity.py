@@ -391,6 +391,14 @@ def test_poisson_nll_against_oracle(osc, ctx):
     for k in range(n_hist):
         want = oracle.poisson_nll(mu[k, :nb], data[k % n_data])
         assert got[k] == pytest.approx(want, rel=1e-12), k
+    # an exposure scale: mu = 0.37 * hist (one rounding on both sides)
+    ctx.osc_poisson_nll(dev(mu), dev(data), out, mu_scale=0.37)
+    got = host(out)
+    for k in range(n_hist):
+        want = oracle.poisson_nll(0.37 * mu[k, :nb], data[k % n_data])
+        assert got[k] == pytest.approx(want, rel=1e-12), k
+    with pytest.raises(osc.OscError):
+        ctx.osc_poisson_nll(dev(mu), dev(data), out, mu_scale=0.0)
 
 
 def test_poisson_nll_on_fitter_loop(osc, ctx):

@@ -125,3 +125,48 @@ def test_server_poisson_stream(osc, ctx, resident):
     for k in (0, 57, 199):
         p, s, t = reqs[k]
         np.testing.assert_array_equal(res[k], plain(osc, ctx, ds[s], p, t))
+
+
+def test_server_likelihood_and_mcmc(osc, ctx, resident):
+    """Sec. 2.2's fitter loop: with data rows set, every request returns
+    -2 ln L (Eq. 2) of mu_scale * hist against its sample's row, the value
+    the oracle gives for the same histogram; Metropolis chains over the
+    server are reproducible and move towards the generating point."""
+    import oracle
+    from paper_1311_7579_amd import serving
+    samples, ds = resident
+    truth = workload.TABLE1
+    pdfs = np.array([plain(osc, ctx, d, truth, osc.OSC_FP64) for d in ds])
+    rng = np.random.default_rng(71)
+    mu_scale = 3000.0 / pdfs[2, :50].sum()
+    data = rng.poisson(mu_scale * pdfs[:, :50]).astype(float)
+    server = osc.Server(ctx, ds, 50, 0.0, 3.0, slots=4, scratch_budget_bytes=64 << 20)
+    try:
+        r = server.wait(server.submit(truth, 2, osc.OSC_FP64))
+        assert np.isnan(r.nll)
+        server.set_data(data, mu_scale)
+        probe = [truth, dict(truth, sin2_th23=0.42), dict(truth, dm2_32=2.25e-3)]
+        for k, p in enumerate(probe):
+            for s in (1, 2):
+                r = server.wait(server.submit(p, s, osc.OSC_FP64))
+                want = oracle.poisson_nll(mu_scale * r.hist[:50], data[s])
+                assert r.nll == pytest.approx(want, rel=1e-12), (k, s)
+        kw = dict(start=dict(truth, sin2_th23=0.43, dm2_32=2.3e-3),
+                  free=("sin2_th23", "dm2_32"), sigmas=(0.02, 3e-5),
+                  bounds=((0.3, 0.7), (2.0e-3, 2.8e-3)), n_chains=3, n_steps=60, seed=9,
+                  sample=2)
+        a = serving.run_mcmc(server, **kw)
+        b = serving.run_mcmc(server, **kw)
+        np.testing.assert_array_equal(a["chains"], b["chains"])
+        np.testing.assert_array_equal(a["nll"], b["nll"])
+        assert 0.0 < a["acceptance"] < 1.0
+        # the chains end closer (in -2 ln L) to the generating point than they start
+        assert np.all(a["nll"][:, -1] < a["nll"][:, 0])
+        server.set_data(None)
+        assert np.isnan(server.wait(server.submit(truth, 0, osc.OSC_FP64)).nll)
+        with pytest.raises(ValueError):
+            server.set_data(data[:2], mu_scale)
+        with pytest.raises(osc.OscError):
+            server.set_data(data, -1.0)
+    finally:
+        server.close()
