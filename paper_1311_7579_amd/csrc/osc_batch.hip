@@ -344,7 +344,7 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
     }
     b->plan = osc::plan_merge(b->tiles.data(), n_samples, nbt);
     for (int s = 0; s < n_samples; ++s)
-        hs[size_t(s)].row0 = b->plan.levels[0].chunk0[s] * osc::kMergeChunkTiles;
+        hs[size_t(s)].row0 = b->plan.levels[0].in_row0[s];
 
     hipDeviceProp_t prop;
     int occ = 0;

@@ -558,41 +558,48 @@ __device__ __forceinline__ double wave_tree(double v)
     return v;
 }
 
-// Complete binary tree over the kMergeChunkTiles rows of one bin held
-// contiguously at src (rows at or beyond `count` are +0.0): lane l adds
-// rows 2l and 2l + 1, the wave butterfly does the rest.
-__device__ __forceinline__ double chunk_sum(const double* __restrict__ src, int64_t first,
-                                            int64_t count, int lane)
-{
-    const int64_t e = first + 2 * lane;
-    const double a = e < count ? src[2 * lane] : 0.0;
-    const double b = e + 1 < count ? src[2 * lane + 1] : 0.0;
-    return wave_tree(a + b);
-}
-
-// One merge level (see MergeLevel): wave w of block (gc, g, set) reduces
-// chunk gc of the set's input rows for bin g * kMergeWaves + w.  One bin per
-// wave keeps every chunk sum of a level in flight at once.
+// One merge level (see MergeLevel): block (gc, bin, set) reduces chunk gc
+// of the set's input rows for one bin.  Thread t adds its 64 contiguous
+// rows (+0.0 beyond the sample's rows) as a binary tree in registers; the
+// 64 lanes of a wave meet in the butterfly tree and the block's waves in a
+// last tree step.
 template <bool FINAL>
 __device__ __forceinline__ void merge_level_block(const MergeLevel& L, const double* __restrict__ in,
                                                   double* __restrict__ out)
 {
+    __shared__ double wave_sum[kMergeWaves];
     const int nbt = L.nbt;
-    const int b = int(blockIdx.y) * kMergeWaves + int(threadIdx.x >> 6);
-    if (b >= nbt) return;
+    const int bin = int(blockIdx.y);
     const int64_t gc = blockIdx.x, set = blockIdx.z;
     int s = 0;
     while (s + 1 < L.n_samples && gc >= L.chunk0[s + 1]) ++s;
     const int64_t c = gc - L.chunk0[s];
-    const int lane = threadIdx.x & 63;
-    const double* src =
-        in + set * L.set_stride_in + (gc * int64_t(nbt) + b) * kMergeChunkTiles;
-    const double r = chunk_sum(src, c * kMergeChunkTiles, L.rows[s], lane);
-    if (lane == 0) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t first = c * kMergeChunkRows + int64_t(t) * kMergeThreadRows;
+    const int64_t count = L.rows[s] - first;
+    const double* src = in + set * L.set_stride_in + partial_index(L.in_row0[s] + first, bin, nbt);
+    double v[kMergeThreadRows];
+    if (count >= kMergeThreadRows) {
+#pragma unroll
+        for (int i = 0; i < kMergeThreadRows; ++i) v[i] = src[i];
+    } else {
+#pragma unroll
+        for (int i = 0; i < kMergeThreadRows; ++i) v[i] = i < count ? src[i] : 0.0;
+    }
+#pragma unroll
+    for (int w = kMergeThreadRows / 2; w >= 1; w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w; ++i) v[i] = v[2 * i] + v[2 * i + 1];
+    const double r = wave_tree(v[0]);
+    if (lane == 0) wave_sum[wave] = r;
+    __syncthreads();
+    if (t == 0) {
+        static_assert(kMergeWaves == 4, "the block tree below is written for four waves");
+        const double total = (wave_sum[0] + wave_sum[1]) + (wave_sum[2] + wave_sum[3]);
         if (FINAL)
-            out[(set * L.n_samples + s) * nbt + b] = r;
+            out[(set * L.n_samples + s) * nbt + bin] = total;
         else
-            out[set * L.set_stride_out + partial_index(L.out_row0[s] + c, b, nbt)] = r;
+            out[set * L.set_stride_out + partial_index(L.out_row0[s] + c, bin, nbt)] = total;
     }
 }
 

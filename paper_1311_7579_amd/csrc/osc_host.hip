@@ -113,8 +113,9 @@ namespace {
 struct Scratch {
     void* ptr = nullptr;
     size_t cap = 0;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;      // recorded after the slot's last use
     bool recorded = false;
+    hipStream_t last = nullptr;     // stream of the slot's last use
 };
 
 constexpr int kScratchSlots = 4;
@@ -176,8 +177,9 @@ void prof_mark(hipEvent_t ev, hipStream_t stream)
     if (ev) (void)hipEventRecord(ev, stream);
 }
 
-// Scratch for one call on `stream`: slots are used round-robin; a reused
-// slot orders the new stream after the last kernel that read it.
+// Scratch for one call on `stream`: slots are used round-robin; a slot last
+// used on another stream orders the new stream after that use (a wait on
+// its event); on the same stream the stream order already does.
 osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scratch** out)
 {
     Scratch& s = ctx->scratch[ctx->next_scratch];
@@ -198,7 +200,7 @@ osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scrat
         }
         s.cap = want;
         s.recorded = false;
-    } else if (s.recorded) {
+    } else if (s.recorded && s.last != stream) {
         if (hipStreamWaitEvent(stream, s.done, 0) != hipSuccess) return OSC_ERR_DEVICE;
     }
     *out = &s;
@@ -209,6 +211,7 @@ osc_status release_scratch(Scratch* s, hipStream_t stream)
 {
     if (hipEventRecord(s->done, stream) != hipSuccess) return OSC_ERR_DEVICE;
     s->recorded = true;
+    s->last = stream;
     return OSC_OK;
 }
 

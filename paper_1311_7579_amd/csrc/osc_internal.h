@@ -36,29 +36,37 @@ constexpr int kLayeredWavesPerSimd = 3;
 
 // Largest event count accepted.
 constexpr int64_t kMaxEvents = int64_t(1) << 32;
-// Histogram merge: launches in which each wave reduces an aligned chunk of
-// kMergeChunkTiles rows (tile results, then chunk results) of one bin,
-// level by level until one row per histogram is left.  Rows are stored
-// bin-major within each chunk (partial_index).
+// Histogram merge: launches of 256-thread blocks, one block per (chunk of
+// kMergeChunkRows rows, bin, parameter set); thread t of a block adds rows
+// 64 t .. 64 t + 63 of its chunk as a binary tree, and the block's threads
+// meet in a binary tree -- one aligned subtree of the tile tree per block.
+// Levels repeat until one row per histogram is left (one level up to
+// kMergeChunkRows tiles, i.e. 1.6e7 events, per sample).  Rows are stored
+// bin-major within chunks of kLayoutChunk rows (partial_index), so a
+// thread's 64 rows of one bin are contiguous.
 constexpr int kMergeThreads = 256;
 constexpr int kMergeWaves = kMergeThreads / 64;
-constexpr int kMergeChunkTiles = 128;
+constexpr int kMergeThreadRows = 64;
+constexpr int64_t kMergeChunkRows = int64_t(kMergeThreads) * kMergeThreadRows;
+constexpr int kLayoutChunk = 128;
 constexpr int kMaxBatchSamples = 16;
 // Largest number of parameter sets of one batch (the merge grid's z extent).
 constexpr int kMaxBatchSets = 65535;
 
 // One level of the merge for n_samples samples (x any number of parameter
-// sets, one set per grid layer z): sample s has rows[s] input rows stored from
-// row 128 * chunk0[s] of the set's input region and produces
-// ceil(rows[s] / 128) (at least one) output rows, stored from row
-// out_row0[s] of the set's output region.  The final level writes
-// hist[set][sample][bin] instead.
+// sets, one set per grid layer z): sample s has rows[s] input rows stored
+// from row in_row0[s] (a multiple of kLayoutChunk) of the set's input
+// region, takes blocks chunk0[s] .. and produces ceil(rows[s] /
+// kMergeChunkRows) (at least one) output rows, stored from row out_row0[s]
+// (a multiple of kLayoutChunk) of the set's output region.  The final level
+// writes hist[set][sample][bin] instead.
 struct MergeLevel {
     int32_t n_samples;
     int32_t nbt;
-    int64_t total_chunks;                 // blocks per set
+    int64_t total_chunks;                 // blocks per (bin, set)
     int64_t set_stride_in, set_stride_out;
     int64_t rows[kMaxBatchSamples];
+    int64_t in_row0[kMaxBatchSamples];
     int64_t chunk0[kMaxBatchSamples];
     int64_t out_row0[kMaxBatchSamples];
 };
@@ -66,8 +74,8 @@ struct MergeLevel {
 // Position of the result of (tile, bin) among the tile results.
 __host__ __device__ inline int64_t partial_index(int64_t tile, int bin, int nbt)
 {
-    return (tile / kMergeChunkTiles) * int64_t(nbt) * kMergeChunkTiles +
-           int64_t(bin) * kMergeChunkTiles + (tile % kMergeChunkTiles);
+    return (tile / kLayoutChunk) * int64_t(nbt) * kLayoutChunk + int64_t(bin) * kLayoutChunk +
+           (tile % kLayoutChunk);
 }
 
 // One flavour channel (beta <- alpha) of the vacuum mass matrix H0 =

@@ -196,36 +196,45 @@ hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
 
 MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt)
 {
+    auto align = [](int64_t r) { return (r + kLayoutChunk - 1) / kLayoutChunk * kLayoutChunk; };
     MergePlan p;
     p.nbt = nbt;
     p.n_samples = n_samples;
     std::vector<int64_t> rows(tiles, tiles + n_samples);
+    std::vector<int64_t> row0(static_cast<size_t>(n_samples), 0);
+    int64_t in_rows = 0;
+    for (int s = 0; s < n_samples; ++s) {
+        row0[size_t(s)] = in_rows;
+        in_rows += align(rows[size_t(s)]);
+    }
     int64_t level_max = 0;
-    bool first = true;
-    for (;;) {
+    for (bool first = true;; first = false) {
         MergeLevel L{};
         L.n_samples = n_samples;
         L.nbt = nbt;
         int64_t chunks = 0, out_rows = 0;
         bool final_level = true;
         for (int s = 0; s < n_samples; ++s) {
-            const int64_t ch = rows[s] > kMergeChunkTiles ? (rows[s] + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
-            L.rows[s] = rows[s];
+            const int64_t r = rows[size_t(s)];
+            const int64_t ch = r > kMergeChunkRows ? (r + kMergeChunkRows - 1) / kMergeChunkRows : 1;
+            L.rows[s] = r;
+            L.in_row0[s] = row0[size_t(s)];
             L.chunk0[s] = chunks;
-            L.out_row0[s] = out_rows * kMergeChunkTiles;
+            L.out_row0[s] = out_rows;
             chunks += ch;
-            out_rows += ch > kMergeChunkTiles ? (ch + kMergeChunkTiles - 1) / kMergeChunkTiles : 1;
+            out_rows += align(ch);
             if (ch > 1) final_level = false;
-            rows[s] = ch;
+            rows[size_t(s)] = ch;
+            row0[size_t(s)] = L.out_row0[s];
         }
         L.total_chunks = chunks;
-        L.set_stride_in = chunks * kMergeChunkTiles * nbt;
-        L.set_stride_out = final_level ? 0 : out_rows * kMergeChunkTiles * nbt;
+        L.set_stride_in = in_rows * nbt;
+        L.set_stride_out = final_level ? 0 : out_rows * nbt;
         if (first) p.tile_set_stride = L.set_stride_in;
         else level_max = std::max(level_max, L.set_stride_in);
         if (!final_level) level_max = std::max(level_max, L.set_stride_out);
-        first = false;
         p.levels.push_back(L);
+        in_rows = out_rows;
         if (final_level) break;
     }
     p.level_set_stride = level_max;
@@ -245,8 +254,7 @@ hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, dou
     const double* in = scratch;
     for (size_t l = 0; l < p.levels.size(); ++l) {
         const MergeLevel& L = p.levels[l];
-        const dim3 grid{unsigned(L.total_chunks), unsigned((p.nbt + kMergeWaves - 1) / kMergeWaves),
-                        unsigned(n_sets)};
+        const dim3 grid{unsigned(L.total_chunks), unsigned(p.nbt), unsigned(n_sets)};
         const bool final_level = l + 1 == p.levels.size();
         double* out = final_level ? hist_out : bufs[l % 2];
         if (final_level)
