@@ -69,7 +69,7 @@ __global__ void reset_queue(unsigned* queue)
 
 template <bool MIXED>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kBatchWavesPerSimd)))
-void batch_kernel(BatchArgs a,
+void batch_kernel(BatchArgs a, SinCosTable sctab,
                                                            const BatchSampleDev* __restrict__ samples,
                                                            const SetConsts* __restrict__ sets,
                                                            double* __restrict__ partial,
@@ -77,8 +77,10 @@ void batch_kernel(BatchArgs a,
 {
     extern __shared__ double hist[];
     __shared__ Chan tab[kChannels];
+    __shared__ SinCos sct[64];
     const int lane = threadIdx.x;
     const int nbt = a.nbt;
+    if (!MIXED) load_sincos(sctab, sct, lane);   // read after the first barrier below
 
     int64_t item = a.dynamic ? take_item(queue, lane) : int64_t(blockIdx.x);
     while (item < a.n_items) {
@@ -100,7 +102,7 @@ void batch_kernel(BatchArgs a,
             load_tab(sc, tab, lane);
             hist_zero(hist, lane, nbt);
             __syncthreads();
-            const ConstDensityProb<MIXED> prob{&sc, tab, S.pc.kA, S.pc.kL};
+            const ConstDensityProb<MIXED> prob{&sc, tab, sct, S.pc.kA, S.pc.kL};
             if (full)
                 tile_events<kPdf, false, true>(prob, a.bc, hist, lane, base, S.n, S.e_true,
                                                S.flags, S.weight, S.e_reco, nullptr, nullptr);
@@ -192,12 +194,15 @@ hipError_t enqueue(osc_batch* b, int n_sets, const osc_batch_config& c, hipStrea
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
+        const osc::SinCosTable& sct = osc::host::sincos_table();
         if (b->precision == OSC_FP32_MIXED)
             hipLaunchKernelGGL(osc::batch_kernel<true>, dim3(unsigned(grid)), dim3(osc::kTileLanes),
-                               lds, stream, a, b->d_samples, b->d_sets, b->d_scratch, b->d_queue);
+                               lds, stream, a, sct, b->d_samples, b->d_sets, b->d_scratch,
+                               b->d_queue);
         else
             hipLaunchKernelGGL(osc::batch_kernel<false>, dim3(unsigned(grid)), dim3(osc::kTileLanes),
-                               lds, stream, a, b->d_samples, b->d_sets, b->d_scratch, b->d_queue);
+                               lds, stream, a, sct, b->d_samples, b->d_sets, b->d_scratch,
+                               b->d_queue);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

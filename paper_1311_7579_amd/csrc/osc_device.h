@@ -20,64 +20,49 @@ static_assert(kLaneEvents % kGroup == 0, "the group size divides the events per 
 
 // ---------------------------------------------------------------------------
 // FP64 sine and cosine of a phase (|x| up to ~1e6 rad).
-// Cody-Waite reduction by pi/2 with a two-term constant (FMA form), then
-// the Taylor series of sin to r^15 and of cos to r^16 on |r| <= pi/4
-// (truncation below 5e-17), then the quadrant rotation.
+// x = n pi/32 + r with a two-term Cody-Waite reduction (FMA form), |r| <=
+// pi/64; sin r and cos r from their Taylor series to r^9 and r^8
+// (truncation below 1e-19 on that interval); then the angle-addition
+// formulas with sin and cos of (n mod 64) pi/32 from a table in LDS.
 // ---------------------------------------------------------------------------
-constexpr double kTwoOverPi = 0.63661977236758134308;
-constexpr double kPiOver2Hi = 1.5707963267948966192;        // fl(pi/2)
-constexpr double kPiOver2Lo = 6.123233995736766036e-17;      // fl(pi/2 - fl(pi/2))
+constexpr double kInvStep = 10.185916357881301489;        // 32 / pi
+constexpr double kStepHi = 0.098174770424681034820;       // fl(pi / 32)
+constexpr double kStepLo = 3.827021247335479e-18;         // fl(pi / 32 - fl(pi / 32))
 
 // (-1)^k / (2k+1)!  and  (-1)^k / (2k)!
-constexpr double kS1 = -1.0 / 6.0;
-constexpr double kS2 = 1.0 / 120.0;
-constexpr double kS3 = -1.0 / 5040.0;
-constexpr double kS4 = 1.0 / 362880.0;
-constexpr double kS5 = -1.0 / 39916800.0;
-constexpr double kS6 = 1.0 / 6227020800.0;
-constexpr double kS7 = -1.0 / 1307674368000.0;
-constexpr double kC1 = -1.0 / 2.0;
-constexpr double kC2 = 1.0 / 24.0;
-constexpr double kC3 = -1.0 / 720.0;
-constexpr double kC4 = 1.0 / 40320.0;
-constexpr double kC5 = -1.0 / 3628800.0;
-constexpr double kC6 = 1.0 / 479001600.0;
-constexpr double kC7 = -1.0 / 87178291200.0;
-constexpr double kC8 = 1.0 / 20922789888000.0;
+constexpr double kS3 = -1.0 / 6.0;
+constexpr double kS5 = 1.0 / 120.0;
+constexpr double kS7 = -1.0 / 5040.0;
+constexpr double kS9 = 1.0 / 362880.0;
+constexpr double kC2 = -1.0 / 2.0;
+constexpr double kC4 = 1.0 / 24.0;
+constexpr double kC6 = -1.0 / 720.0;
+constexpr double kC8 = 1.0 / 40320.0;
 
 __device__ __forceinline__ double flip_sign(double v, uint32_t sign_bit)
 {
     return __hiloint2double(__double2hiint(v) ^ int(sign_bit), __double2loint(v));
 }
 
-__device__ __forceinline__ void phase_sincos(double x, double& sn, double& cs)
+__device__ __forceinline__ void phase_sincos(double x, const SinCos* __restrict__ table,
+                                             double& sn, double& cs)
 {
-    const double n = __builtin_rint(x * kTwoOverPi);
-    double r = fma(-n, kPiOver2Hi, x);
-    r = fma(-n, kPiOver2Lo, r);
+    const double n = __builtin_rint(x * kInvStep);
+    double r = fma(-n, kStepHi, x);
+    r = fma(-n, kStepLo, r);
+    const SinCos a = table[int(n) & 63];
     const double z = r * r;
-    double ps = fma(z, kS7, kS6);
-    ps = fma(z, ps, kS5);
-    ps = fma(z, ps, kS4);
-    ps = fma(z, ps, kS3);
-    ps = fma(z, ps, kS2);
-    ps = fma(z, ps, kS1);
+    const double ps = fma(z, fma(z, fma(z, kS9, kS7), kS5), kS3);
     const double s = fma(r * z, ps, r);
-    double pc = fma(z, kC8, kC7);
-    pc = fma(z, pc, kC6);
-    pc = fma(z, pc, kC5);
-    pc = fma(z, pc, kC4);
-    pc = fma(z, pc, kC3);
-    pc = fma(z, pc, kC2);
-    pc = fma(z, pc, kC1);
-    const double c = fma(z, pc, 1.0);
-    // quadrant q = n mod 4: sin = (s, c, -s, -c)[q], cos = (c, -s, -c, s)[q]
-    const int q = int(n);
-    const bool swap = (q & 1) != 0;
-    const uint32_t sgn_s = uint32_t(q << 30) & 0x80000000u;
-    const uint32_t sgn_c = uint32_t((q + 1) << 30) & 0x80000000u;
-    sn = flip_sign(swap ? c : s, sgn_s);
-    cs = flip_sign(swap ? s : c, sgn_c);
+    const double c = fma(z, fma(z, fma(z, fma(z, kC8, kC6), kC4), kC2), 1.0);
+    sn = fma(a.s, c, a.c * s);
+    cs = fma(a.c, c, -(a.s * s));
+}
+
+// Copy the sin/cos anchors into LDS (the 64 lanes of a wave, one each).
+__device__ __forceinline__ void load_sincos(const SinCosTable& t, SinCos* lds, int lane)
+{
+    if (lane < 64) lds[lane] = t.e[lane];
 }
 
 // Mixed tier: the phase is reduced modulo 2 pi in FP64 (two-term
@@ -116,19 +101,16 @@ __device__ __forceinline__ double recip_coarse(double y)
     return fma(r, fma(-y, r, 1.0), r);
 }
 
-// arccos on [-1, 1] in FP32: Abramowitz & Stegun 4.4.46 on |x| (error
-// <= 2.2e-8 rad) and acos(-x) = pi - acos(x).
-__device__ __forceinline__ float acos_f32(float x)
+// arccos on [-1, 1] in FP32 for the eigenvalue seeds: Abramowitz & Stegun
+// 4.4.45 on |x| (error <= 6.7e-5 rad; the FP64 refinement below absorbs
+// seed errors far larger than that) and acos(-x) = pi - acos(x).
+__device__ __forceinline__ float acos_seed(float x)
 {
     const float ax = __builtin_fabsf(x);
-    float p = -0.0012624911f;
-    p = __builtin_fmaf(p, ax, 0.0066700901f);
-    p = __builtin_fmaf(p, ax, -0.0170881256f);
-    p = __builtin_fmaf(p, ax, 0.0308918810f);
-    p = __builtin_fmaf(p, ax, -0.0501743046f);
-    p = __builtin_fmaf(p, ax, 0.0889789874f);
-    p = __builtin_fmaf(p, ax, -0.2145988016f);
-    p = __builtin_fmaf(p, ax, 1.5707963050f);
+    float p = -0.0187293f;
+    p = __builtin_fmaf(p, ax, 0.0742610f);
+    p = __builtin_fmaf(p, ax, -0.2121144f);
+    p = __builtin_fmaf(p, ax, 1.5707288f);
     const float r = __builtin_amdgcn_sqrtf(1.0f - ax) * p;
     return x < 0.0f ? 3.14159265358979f - r : r;
 }
@@ -138,40 +120,48 @@ __device__ __forceinline__ float acos_f32(float x)
 // solution x = tr/3 + (2/3) sqrt(p) cos(theta - 2 pi k / 3),
 // theta = acos(q / (2 p^1.5)) / 3 (p = tr^2 - 3 c1, q = 2 tr^3 - 9 tr c1 +
 // 27 det), each refined in FP64 by one Halley and one Newton step on f; the
-// third root follows from the trace.
+// third root follows from the trace.  The two roots' divisions of each
+// step share one reciprocal: 1/a = b / (a b), 1/b = a / (a b).
 __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
                                             double& l0, double& l1, double& l2)
 {
     const double p = fma(tr, tr, -3.0 * c1);
     const double q = fma(tr, fma(2.0 * tr, tr, -9.0 * c1), 27.0 * det);
     const float pf = float(p), qf = float(q);
-    const float spf = __builtin_amdgcn_sqrtf(pf);
-    float rf = qf * __builtin_amdgcn_rcpf(2.0f * pf * spf);
+    const float rs = __builtin_amdgcn_rsqf(pf);                 // p^-1/2
+    float rf = 0.5f * qf * (rs * rs * rs);                      // q / (2 p^3/2)
     rf = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, rf));
     // theta in revolutions for the hardware cosine: acos(r) / (3 * 2 pi)
-    const float th = acos_f32(rf) * 0.053051647697298445f;
-    const double k = double((2.0f / 3.0f) * spf);
+    const float th = acos_seed(rf) * 0.053051647697298445f;
+    const double k = double((2.0f / 3.0f) * (pf * rs));
     const double t3 = tr * (1.0 / 3.0);
-    double x[2];
-    x[0] = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
-    x[1] = fma(k, double(__builtin_amdgcn_cosf(th - 0.33333333f)), t3);
+    double x0 = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
+    double x1 = fma(k, double(__builtin_amdgcn_cosf(th - 0.33333333f)), t3);
     const double tr2 = 2.0 * tr;
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        double y = x[j];
-        // Halley: y -= 2 f f' / (2 f'^2 - f f'')
-        double f = fma(fma(y - tr, y, c1), y, -det);
-        double fp = fma(y, fma(3.0, y, -tr2), c1);
-        const double fpp = fma(6.0, y, -tr2);
-        y -= (f * fp) * recip_coarse(fma(fp, fp, -0.5 * f * fpp));
-        // Newton: y -= f / f'
-        f = fma(fma(y - tr, y, c1), y, -det);
-        fp = fma(y, fma(3.0, y, -tr2), c1);
-        y -= f * recip_coarse(fp);
-        x[j] = y;
+    // Halley: x -= 2 f f' / (2 f'^2 - f f'')
+    {
+        const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
+        const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
+        const double g0 = fma(x0, fma(3.0, x0, -tr2), c1);
+        const double g1 = fma(x1, fma(3.0, x1, -tr2), c1);
+        const double d0 = fma(g0, g0, -0.5 * f0 * fma(6.0, x0, -tr2));
+        const double d1 = fma(g1, g1, -0.5 * f1 * fma(6.0, x1, -tr2));
+        const double r = recip_coarse(d0 * d1);
+        x0 -= (f0 * g0) * (d1 * r);
+        x1 -= (f1 * g1) * (d0 * r);
     }
-    l0 = x[0];
-    l1 = x[1];
+    // Newton: x -= f / f'
+    {
+        const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
+        const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
+        const double g0 = fma(x0, fma(3.0, x0, -tr2), c1);
+        const double g1 = fma(x1, fma(3.0, x1, -tr2), c1);
+        const double r = recip_coarse(g0 * g1);
+        x0 -= f0 * (g1 * r);
+        x1 -= f1 * (g0 * r);
+    }
+    l0 = x0;
+    l1 = x1;
     l2 = (tr - l0) - l1;
 }
 
@@ -182,7 +172,8 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
 // are formed.
 template <bool MIXED>
 __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* tab,
-                                             double kA, double kL, double E, uint32_t f)
+                                             const SinCos* sct, double kA, double kL, double E,
+                                             uint32_t f)
 {
     // flag byte: alpha bits 0-1, beta bits 2-3, antineutrino bit 4
     const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
@@ -216,8 +207,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
     double P;
     if constexpr (!MIXED) {
         double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, s2, c2);   // phi_2 - phi_0
+        phase_sincos(-d01 * ph, sct, s1, c1);   // phi_1 - phi_0
+        phase_sincos(-d02 * ph, sct, s2, c2);   // phi_2 - phi_0
         const double x0r = fma(v0, dba, fma(-u0, mre, m2re)) * iD0;
         const double x0i = fma(-u0, mim, m2im) * iD0;
         const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
@@ -258,10 +249,11 @@ template <bool MIXED>
 struct ConstDensityProb {
     const SetConsts* sc;
     const Chan* tab;
+    const SinCos* sct;
     double kA, kL;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
-        return event_prob<MIXED>(*sc, tab, kA, kL, E, f);
+        return event_prob<MIXED>(*sc, tab, sct, kA, kL, E, f);
     }
 };
 
@@ -275,7 +267,8 @@ struct ConstDensityProb {
 // matrix of the layer (H0 + A e_e e_e^T, conjugated with A -> -A for
 // antineutrinos); its entries come from the channel table.
 __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const Chan* tab,
-                                                     const LayerPath& lp, double E, uint32_t f)
+                                                     const SinCos* sct, const LayerPath& lp,
+                                                     double E, uint32_t f)
 {
     const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
     const uint32_t a = min(f & 3u, 2u), b = min((f >> 2) & 3u, 2u);
@@ -301,8 +294,8 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
         const double invQ = recip(d01 * d02 * d12);
         const double ph = pc.kL * invE;
         double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, s2, c2);   // phi_2 - phi_0
+        phase_sincos(-d01 * ph, sct, s1, c1);   // phi_1 - phi_0
+        phase_sincos(-d02 * ph, sct, s2, c2);   // phi_2 - phi_0
         // c_k = exp(-i dphi_k) / D_k (c_0 real)
         const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
         const double k1r = c1 * iD1, k1i = -s1 * iD1;
@@ -356,10 +349,11 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
 struct LayeredProb {
     const SetConsts* sc;
     const Chan* tab;
+    const SinCos* sct;
     const LayerPath* lp;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
-        return event_prob_layered(*sc, tab, *lp, E, f);
+        return event_prob_layered(*sc, tab, sct, *lp, E, f);
     }
 };
 

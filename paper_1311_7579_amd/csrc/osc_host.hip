@@ -252,6 +252,20 @@ osc::BinConsts osc::host::bin_consts(const osc_binning* b)
 
 int osc::host::ctx_device(const osc_ctx* ctx) { return ctx->device; }
 
+const osc::SinCosTable& osc::host::sincos_table()
+{
+    static const osc::SinCosTable table = [] {
+        osc::SinCosTable t{};
+        const long double pi = 3.141592653589793238462643383279502884L;
+        for (int k = 0; k < 64; ++k) {
+            const long double a = pi * static_cast<long double>(k) / 32.0L;
+            t.e[k] = osc::SinCos{static_cast<double>(std::sin(a)), static_cast<double>(std::cos(a))};
+        }
+        return t;
+    }();
+    return table;
+}
+
 bool osc::host::ctx_set(osc_ctx* ctx, int32_t set, osc::SetConsts* out)
 {
     std::lock_guard<std::mutex> lock(ctx->mu);

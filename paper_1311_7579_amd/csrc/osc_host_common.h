@@ -11,6 +11,8 @@ namespace host {
 // Parameter-only quantities of one set (mixing matrix, flavour-basis
 // vacuum mass matrix and its square, cubic constants, channel table).
 SetConsts set_consts(const osc_params& p);
+// sin / cos of k pi / 32 rounded to FP64 (from long double sinl / cosl).
+const SinCosTable& sincos_table();
 PathConsts path_consts(const osc_sample* s);
 BinConsts bin_consts(const osc_binning* b);
 bool sample_ok(const osc_sample* s, bool needs_hist_inputs);

@@ -104,6 +104,15 @@ struct SetConsts {
     Chan ch[kChannels];
 };
 
+// sin and cos of k pi / 32, k = 0..63 (the anchors of the FP64 phase
+// sine/cosine), computed once on the host in extended precision.
+struct SinCos {
+    double s, c;
+};
+struct SinCosTable {
+    SinCos e[64];
+};
+
 // Path constants of one sample.
 struct PathConsts {
     double kA;   // matter term per GeV: A = +-kA * E (eV^2)

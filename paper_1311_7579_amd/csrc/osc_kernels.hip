@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "osc_device.h"
+#include "osc_host_common.h"
 #include "osc_internal.h"
 #include "osc_launch.h"
 
@@ -28,7 +29,7 @@ using namespace dev;
 template <int MODE, bool WRITE_P, bool MIXED = false>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kTileWavesPerSimd)))
 void tile_kernel(
-    SetConsts sc, PathConsts pc, BinConsts bc, int64_t n, int64_t ntiles,
+    SetConsts sc, SinCosTable sctab, PathConsts pc, BinConsts bc, int64_t n, int64_t ntiles,
     const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
     const double* __restrict__ weight, const double* __restrict__ e_reco,
     const double* __restrict__ value, double* __restrict__ p_out,
@@ -36,17 +37,21 @@ void tile_kernel(
 {
     extern __shared__ double hist[];
     __shared__ Chan tab[kChannels];
+    __shared__ SinCos sct[64];
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int64_t base = tile * kTileEvents + lane;
     const int nbt = bc.nb + 2;
 
-    if (MODE != kHist) load_tab(sc, tab, lane);
+    if (MODE != kHist) {
+        load_tab(sc, tab, lane);
+        if (!MIXED) load_sincos(sctab, sct, lane);
+    }
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
-    const ConstDensityProb<MIXED> prob{&sc, tab, pc.kA, pc.kL};
+    const ConstDensityProb<MIXED> prob{&sc, tab, sct, pc.kA, pc.kL};
     if ((tile + 1) * kTileEvents <= n)
         tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
                                          e_reco, value, p_out);
@@ -63,13 +68,14 @@ void tile_kernel(
 // The same tile body with P through a layered path (FP64 only).
 template <int MODE, bool WRITE_P>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kLayeredWavesPerSimd)))
-void layered_tile_kernel(SetConsts sc, LayerPath lp, BinConsts bc, int64_t n,
+void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConsts bc, int64_t n,
                          const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
                          const double* __restrict__ weight, const double* __restrict__ e_reco,
                          double* __restrict__ p_out, double* __restrict__ partial)
 {
     extern __shared__ double hist[];
     __shared__ Chan tab[kChannels];
+    __shared__ SinCos sct[64];
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
@@ -77,10 +83,11 @@ void layered_tile_kernel(SetConsts sc, LayerPath lp, BinConsts bc, int64_t n,
     const int nbt = bc.nb + 2;
 
     load_tab(sc, tab, lane);
+    load_sincos(sctab, sct, lane);
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
-    const LayeredProb prob{&sc, tab, &lp};
+    const LayeredProb prob{&sc, tab, sct, &lp};
     if ((tile + 1) * kTileEvents <= n)
         tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
                                          e_reco, nullptr, p_out);
@@ -150,10 +157,11 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
     if (ntiles == 0) return hipSuccess;
     const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
     const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
+    const SinCosTable& sctab = host::sincos_table();
 #define OSC_LAUNCH(M, W, X)                                                                      \
     hipExtLaunchKernelGGL((tile_kernel<M, W, X>), grid, block, lds, stream, ev_begin, ev_end, 0,  \
-                          sc, pc, bc, n, ntiles, e_true, flags, weight, e_reco, value, p_out,     \
-                          partial)
+                          sc, sctab, pc, bc, n, ntiles, e_true, flags, weight, e_reco, value,     \
+                          p_out, partial)
     if (mode == kReweight) {
         if (mixed) OSC_LAUNCH(kReweight, true, true);
         else OSC_LAUNCH(kReweight, true, false);
@@ -179,18 +187,19 @@ hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
     if (ntiles == 0) return hipSuccess;
     const size_t lds = mode == kReweight ? 0 : size_t(bc.nb + 2) * kHistLanes * sizeof(double);
     const dim3 grid{unsigned(ntiles)}, block{unsigned(kTileLanes)};
+    const SinCosTable& sctab = host::sincos_table();
     if (mode == kReweight)
         hipExtLaunchKernelGGL((layered_tile_kernel<kReweight, true>), grid, block, lds, stream,
-                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
-                              p_out, partial);
+                              ev_begin, ev_end, 0, sc, sctab, lp, bc, n, e_true, flags, weight,
+                              e_reco, p_out, partial);
     else if (write_p)
         hipExtLaunchKernelGGL((layered_tile_kernel<kPdf, true>), grid, block, lds, stream,
-                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
-                              p_out, partial);
+                              ev_begin, ev_end, 0, sc, sctab, lp, bc, n, e_true, flags, weight,
+                              e_reco, p_out, partial);
     else
         hipExtLaunchKernelGGL((layered_tile_kernel<kPdf, false>), grid, block, lds, stream,
-                              ev_begin, ev_end, 0, sc, lp, bc, n, e_true, flags, weight, e_reco,
-                              p_out, partial);
+                              ev_begin, ev_end, 0, sc, sctab, lp, bc, n, e_true, flags, weight,
+                              e_reco, p_out, partial);
     return hipGetLastError();
 }
 

@@ -90,11 +90,14 @@ __global__ __launch_bounds__(256) void template_sum_kernel(uint32_t n_cells,
 }
 
 // P of the 18 channels at the centre of every true bin, layout P[c][t].
-__global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, PathConsts pc,
-                                                          TrueBins tb, double* __restrict__ P)
+__global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, SinCosTable sctab,
+                                                          PathConsts pc, TrueBins tb,
+                                                          double* __restrict__ P)
 {
     __shared__ Chan tab[kChannels];
+    __shared__ SinCos sct[64];
     load_tab(sc, tab, threadIdx.x);
+    load_sincos(sctab, sct, threadIdx.x);
     __syncthreads();
     const int64_t k = int64_t(blockIdx.x) * 64 + threadIdx.x;
     if (k >= int64_t(kTemplateChannels) * tb.nt) return;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, PathCons
         E = tb.lo + off;
     }
     const uint32_t f = (c % 3u) | (((c / 3u) % 3u) << 2) | ((c / 9u) << 4);
-    P[k] = event_prob<false>(sc, tab, pc.kA, pc.kL, E, f);
+    P[k] = event_prob<false>(sc, tab, sct, pc.kA, pc.kL, E, f);
 }
 
 // hist[r] for one reconstructed bin per wave: lane l adds the terms
@@ -311,7 +314,7 @@ osc_status osc_fill_pdf_bincentre(osc_ctx* ctx, const osc_template* t, int32_t s
     double* P = p_centre_out ? p_centre_out : t->d_P;
     const int64_t K = int64_t(osc::kTemplateChannels) * t->tb.nt;
     hipLaunchKernelGGL(osc::centre_probs_kernel, dim3(blocks_for(K, 64)), dim3(64), 0, s, sc,
-                       t->pc, t->tb, P);
+                       osc::host::sincos_table(), t->pc, t->tb, P);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
         hipLaunchKernelGGL(osc::bincentre_contract_kernel, dim3(unsigned(t->nr + 2)), dim3(64), 0,
