@@ -53,9 +53,9 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122504.1, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 94145.8, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
-    "source_sha256": "e3a8d40f89ab6cbda799f8fdea112edeabfefff6db6aa02f41acb5e415d0a30b",
+    "fetch_kib": 122736.6, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 99086.4, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "source_sha256": "4fdfa6e95494173a6ed462dade0f6cdfbcc77426895fac283d1aa06dd48a19fc",
 }
 
 
@@ -79,6 +79,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-form measurement (256 sets x 4 uneven samples)")
+    ap.add_argument("--no-bincentre", action="store_true",
+                    help="skip the bin-centre measurement (template + binning effect)")
+    ap.add_argument("--no-layered", action="store_true",
+                    help="skip the layered-matter measurement (5-layer Earth path)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run torch device-to-device copies of MIB MiB (HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -497,7 +501,9 @@ def main():
         result["precision_form"] = precision_form(osc, ctx, ds)
     if not args.no_batch:
         result["batched_form"] = batched_form(osc, ctx)
+    if not args.no_bincentre:
         result["bincentre_form"] = bincentre_form(osc, ctx, s, ds, ms_per_step)
+    if not args.no_layered:
         result["layered_form"] = layered_form(osc, ctx)
     if not args.no_serve:
         result["serving_form"] = serving_form(osc, ctx, args.serve_requests)
