@@ -115,6 +115,15 @@ osc_status osc_validate_params(const osc_params* sets, int32_t n_sets);
  * values they were launched with. */
 osc_status osc_set_params(osc_ctx* ctx, const osc_params* sets, int32_t n_sets);
 
+/* One-time check of a sample's per-event domain, which the per-event
+ * kernels do not make: *bad_energy receives the number of events whose
+ * true energy is not finite and > 0 (their P is undefined), *bad_flags the
+ * number with an invalid flag byte (their P is NaN).  Either output may be
+ * NULL.  Synchronous on `stream` (returns after the counts are on the
+ * host). */
+osc_status osc_validate_sample(osc_ctx* ctx, const osc_sample* sample, int64_t* bad_energy,
+                               int64_t* bad_flags, void* stream);
+
 /* Sec. 2.1 (the paper's kernel): write P(alpha -> beta) of every event of
  * `sample` under parameter set `set` to p_out (device, n FP64 entries,
  * event order).  weight and e_reco are not read. */

@@ -93,8 +93,8 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
         while (s + 1 < a.n_samples && gtile >= samples[s + 1].tile0) ++s;
         const BatchSampleDev& S = samples[s];
         const int64_t tile = gtile - S.tile0;
-        const int64_t base = tile * kTileEvents + lane;
-        const bool full = (tile + 1) * kTileEvents <= S.n;
+        const TileArrays t = tile_arrays(tile, S.n, S.e_true, S.flags, S.weight, S.e_reco,
+                                         nullptr, nullptr);
         const int set_end = int(min(int64_t(a.n_sets), (g + 1) * a.sets_per_item));
         for (int set = int(g) * a.sets_per_item; set < set_end; ++set) {
             const SetConsts& sc = sets[set];
@@ -103,12 +103,12 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
             hist_zero(hist, lane, nbt);
             __syncthreads();
             const ConstDensityProb<MIXED> prob{&sc, tab, sct, S.pc.kA, S.pc.kL};
-            if (full)
-                tile_events<kPdf, false, true>(prob, a.bc, hist, lane, base, S.n, S.e_true,
-                                               S.flags, S.weight, S.e_reco, nullptr, nullptr);
+            if (t.n == kTileEvents)
+                tile_events<kPdf, false, true>(prob, a.bc, hist, lane, t.n, t.e_true, t.flags,
+                                               t.weight, t.e_reco, nullptr, nullptr);
             else
-                tile_events<kPdf, false, false>(prob, a.bc, hist, lane, base, S.n, S.e_true,
-                                                S.flags, S.weight, S.e_reco, nullptr, nullptr);
+                tile_events<kPdf, false, false>(prob, a.bc, hist, lane, t.n, t.e_true, t.flags,
+                                                t.weight, t.e_reco, nullptr, nullptr);
             __syncthreads();
             tile_write(hist, lane, nbt, S.row0 + tile, partial + int64_t(set) * a.set_stride);
         }

@@ -1,6 +1,6 @@
 // Device-side building blocks of libosc shared by the plain and the batched
 // kernels: the per-event probability (FP64 and FP32-mixed tiers), the bin
-// index, the lane-private LDS histograms and the tile body.  Both kernels
+// index, the per-wave LDS histograms and the tile body.  Both kernels
 // run the same code, so a batched (set, sample) histogram equals the plain
 // one bit for bit.
 #pragma once
@@ -422,8 +422,12 @@ struct EventIn {
     uint32_t f;
 };
 
+// Event i of a tile (0 <= i < kTileEvents) whose arrays start at the
+// tile's first event; n = the tile's events (kTileEvents when FULL).
+// Tile-relative 32-bit indices let every load use the scalar tile base plus
+// a 32-bit lane offset.
 template <int MODE, bool FULL>
-__device__ __forceinline__ EventIn load_event(int64_t i, int64_t n, const double* e_true,
+__device__ __forceinline__ EventIn load_event(int i, int n, const double* e_true,
                                               const uint8_t* flags, const double* weight,
                                               const double* e_reco, const double* value)
 {
@@ -441,8 +445,8 @@ __device__ __forceinline__ EventIn load_event(int64_t i, int64_t n, const double
 // dummy inputs), then stored, binned and accumulated in ascending m.
 template <int MODE, bool WRITE_P, bool FULL, class PROB>
 __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc, double* hist,
-                                           int lane, int64_t i0, int64_t n,
-                                           const EventIn (&ev)[kGroup], double* p_out)
+                                           int lane, int i0, int n, const EventIn (&ev)[kGroup],
+                                           double* p_out)
 {
     double P[kGroup], k[kGroup];
     bool edge[kGroup];
@@ -454,7 +458,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     if (WRITE_P) {
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-            const int64_t i = i0 + int64_t(j) * kTileLanes;
+            const int i = i0 + j * kTileLanes;
             if (FULL || i < n) p_out[i] = P[j];
         }
     }
@@ -469,54 +473,86 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     }
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
-        const int64_t i = i0 + int64_t(j) * kTileLanes;
+        const int i = i0 + j * kTileLanes;
         if (FULL || i < n) {
 #pragma clang fp contract(off)
             const double cval = ev[j].w * P[j];            // rounded, never fused
             const int slot = hslot(lds_bin(k[j], bc), lane & (kHistLanes - 1));
             // The lanes sharing an accumulator add in ascending lane order:
-            // one masked LDS read-add-write per lane group, group after
-            // group.  The DS instructions of a wave execute in order, so a
-            // group reads what the previous group wrote; the empty asm with
-            // a memory clobber keeps the compiler from merging or
-            // reordering the groups (each lane runs only one of them).
+            // one masked LDS atomic add per lane group, group after group.
+            // Within a group the lanes hit distinct accumulators, and the
+            // DS instructions of a wave execute in issue order, so every
+            // accumulator receives its additions in the contract's order
+            // (the LDS adder rounds like v_add_f64: round to nearest even).
+            // The empty asm with a memory clobber keeps the compiler from
+            // merging or reordering the groups.
 #pragma unroll
             for (int p = 0; p < kLaneShare; ++p) {
-                if (lane / kHistLanes == p) hist[slot] = hist[slot] + cval;
+                if (lane / kHistLanes == p)
+                    __hip_atomic_fetch_add(hist + slot, cval, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 asm volatile("" ::: "memory");
             }
         }
     }
 }
 
-// The kLaneEvents events of one lane, fully unrolled: the loads of group
-// g + 1 are issued before group g is computed.
+// The kLaneEvents events of one lane of the tile whose arrays start at the
+// tile's first event (n = the tile's events), fully unrolled: the loads of
+// group g + 1 are issued before group g is computed.
 template <int MODE, bool WRITE_P, bool FULL, class PROB>
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
-                                            int lane, int64_t base, int64_t n,
-                                            const double* e_true, const uint8_t* flags,
-                                            const double* weight, const double* e_reco,
-                                            const double* value, double* p_out)
+                                            int lane, int n, const double* e_true,
+                                            const uint8_t* flags, const double* weight,
+                                            const double* e_reco, const double* value,
+                                            double* p_out)
 {
     constexpr int kGroups = kLaneEvents / kGroup;
     EventIn ev[kGroups][kGroup];
 #pragma unroll
     for (int j = 0; j < kGroup; ++j)
-        ev[0][j] = load_event<MODE, FULL>(base + int64_t(j) * kTileLanes, n, e_true, flags,
-                                          weight, e_reco, value);
+        ev[0][j] = load_event<MODE, FULL>(lane + j * kTileLanes, n, e_true, flags, weight,
+                                          e_reco, value);
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
         if (g + 1 < kGroups) {
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
-                ev[g + 1][j] = load_event<MODE, FULL>(
-                    base + int64_t((g + 1) * kGroup + j) * kTileLanes, n, e_true, flags, weight,
-                    e_reco, value);
+                ev[g + 1][j] = load_event<MODE, FULL>(lane + ((g + 1) * kGroup + j) * kTileLanes,
+                                                      n, e_true, flags, weight, e_reco, value);
         }
-        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane,
-                                        base + int64_t(g * kGroup) * kTileLanes, n, ev[g],
-                                        p_out);
+        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, lane + g * kGroup * kTileLanes, n,
+                                        ev[g], p_out);
     }
+}
+
+// The arrays of one tile: the sample's arrays advanced to the tile's first
+// event (absent arrays stay null) and the tile's event count.
+struct TileArrays {
+    const double* e_true;
+    const uint8_t* flags;
+    const double* weight;
+    const double* e_reco;
+    const double* value;
+    double* p_out;
+    int n;
+};
+
+__device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const double* e_true,
+                                                  const uint8_t* flags, const double* weight,
+                                                  const double* e_reco, const double* value,
+                                                  double* p_out)
+{
+    const int64_t t0 = tile * kTileEvents;
+    TileArrays a;
+    a.e_true = e_true ? e_true + t0 : nullptr;
+    a.flags = flags ? flags + t0 : nullptr;
+    a.weight = weight ? weight + t0 : nullptr;
+    a.e_reco = e_reco ? e_reco + t0 : nullptr;
+    a.value = value ? value + t0 : nullptr;
+    a.p_out = p_out ? p_out + t0 : nullptr;
+    a.n = int(min(n - t0, int64_t(kTileEvents)));
+    return a;
 }
 
 // Copy the channel table of a parameter set into LDS (all lanes of the wave).

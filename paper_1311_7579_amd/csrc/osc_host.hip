@@ -585,6 +585,27 @@ osc_status osc_poisson_nll(osc_ctx* ctx, const double* hist, int64_t n_hist, dou
                                                  nll_out, static_cast<hipStream_t>(stream)));
 }
 
+osc_status osc_validate_sample(osc_ctx* ctx, const osc_sample* sample, int64_t* bad_energy,
+                               int64_t* bad_flags, void* stream)
+{
+    if (!ctx || !sample_ok(sample, false)) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const hipStream_t hs = static_cast<hipStream_t>(stream);
+    unsigned long long* d = nullptr;
+    unsigned long long h[2] = {0, 0};
+    if (hipMalloc(&d, sizeof h) != hipSuccess) return OSC_ERR_OUT_OF_MEMORY;
+    hipError_t e = hipMemsetAsync(d, 0, sizeof h, hs);
+    if (e == hipSuccess)
+        e = osc::launch_validate_sample(sample->n, sample->e_true, sample->flags, d, hs);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    (void)hipFree(d);
+    if (e != hipSuccess) return OSC_ERR_DEVICE;
+    if (bad_energy) *bad_energy = int64_t(h[0]);
+    if (bad_flags) *bad_flags = int64_t(h[1]);
+    return OSC_OK;
+}
+
 void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events, int32_t* accumulators)
 {
     if (tile_lanes) *tile_lanes = osc::kTileLanes;

@@ -4,11 +4,13 @@
 // tile t handles events t*T + m*64 + l, m = 0..K-1 (coalesced SoA loads,
 // software-pipelined one group of kGroup events ahead), computes the oscillation
 // probability of each event in FP64 (flavour basis, one amplitude element
-// per event), optionally writes it, and adds w * P into a lane-private
-// histogram held in LDS.  The 64 lane histograms of the tile meet in a
+// per event), optionally writes it, and adds w * P into a per-wave
+// histogram held in LDS (kHistLanes accumulators per bin, each shared by
+// kLaneShare lanes that add in ascending lane order: masked LDS atomic adds,
+// one lane group after the other).  The accumulators of the tile meet in a
 // fixed binary tree; a merge kernel adds the tile results per bin in a
-// fixed binary tree.  No atomics: the bits of the histogram do not depend
-// on the launch shape.
+// fixed binary tree.  Every addition has a fixed place in that order, so
+// the bits of the histogram do not depend on the launch shape or timing.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -41,7 +43,6 @@ void tile_kernel(
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kTileEvents + lane;
     const int nbt = bc.nb + 2;
 
     if (MODE != kHist) {
@@ -52,12 +53,13 @@ void tile_kernel(
     __syncthreads();
 
     const ConstDensityProb<MIXED> prob{&sc, tab, sct, pc.kA, pc.kL};
-    if ((tile + 1) * kTileEvents <= n)
-        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
-                                         e_reco, value, p_out);
+    const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, value, p_out);
+    if (t.n == kTileEvents)
+        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
+                                         t.e_reco, t.value, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, base, n, e_true, flags, weight,
-                                          e_reco, value, p_out);
+        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
+                                          t.e_reco, t.value, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -79,7 +81,6 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kTileEvents + lane;
     const int nbt = bc.nb + 2;
 
     load_tab(sc, tab, lane);
@@ -88,12 +89,13 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
     __syncthreads();
 
     const LayeredProb prob{&sc, tab, sct, &lp};
-    if ((tile + 1) * kTileEvents <= n)
-        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, base, n, e_true, flags, weight,
-                                         e_reco, nullptr, p_out);
+    const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, p_out);
+    if (t.n == kTileEvents)
+        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
+                                         t.e_reco, nullptr, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, base, n, e_true, flags, weight,
-                                          e_reco, nullptr, p_out);
+        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
+                                          t.e_reco, nullptr, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -134,7 +136,45 @@ __global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restric
     if (lane == 0) out[k] = 2.0 * acc;
 }
 
+// One-time domain check of a sample: counts of events whose true energy
+// is not finite and positive, and of events with an invalid flag byte.
+// Grid-stride loop; per-wave sums, one integer atomic per wave and counter
+// (integer sums: the totals do not depend on the order).
+__global__ __launch_bounds__(256) void validate_sample_kernel(int64_t n,
+                                                              const double* __restrict__ e_true,
+                                                              const uint8_t* __restrict__ flags,
+                                                              unsigned long long* __restrict__ bad)
+{
+    unsigned long long be = 0, bf = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const double e = e_true[i];
+        const uint32_t f = flags[i];
+        be += (e > 0.0 && e <= __DBL_MAX__) ? 0ull : 1ull;   // NaN fails both tests
+        bf += ((f < 32u) && ((kValidFlags >> (f & 31u)) & 1u)) ? 0ull : 1ull;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) {
+        be += __shfl_xor(be, s, 64);
+        bf += __shfl_xor(bf, s, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (be) atomicAdd(&bad[0], be);
+        if (bf) atomicAdd(&bad[1], bf);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_validate_sample(int64_t n, const double* e_true, const uint8_t* flags,
+                                  unsigned long long* bad, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(validate_sample_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, n,
+                       e_true, flags, bad);
+    return hipGetLastError();
+}
 
 hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
                               const double* data, int64_t n_data, int nbins, double* out,

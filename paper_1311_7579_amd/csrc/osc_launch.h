@@ -55,6 +55,11 @@ hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
                               const double* data, int64_t n_data, int nbins, double* out,
                               hipStream_t stream);
 
+// Adds to bad[0] the events of the sample whose true energy is not finite
+// and positive and to bad[1] those with an invalid flag byte.
+hipError_t launch_validate_sample(int64_t n, const double* e_true, const uint8_t* flags,
+                                  unsigned long long* bad, hipStream_t stream);
+
 // Resident one-wave blocks per CU of the per-event kernel of `mode` for
 // histograms of nbins bins.
 hipError_t occupancy(int mode, int nbins, int* blocks_per_cu);

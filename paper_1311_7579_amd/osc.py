@@ -133,6 +133,9 @@ def load():
     L.osc_batch_create.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                    ctypes.c_int, i32, ctypes.POINTER(vp)]
     L.osc_batch_create.restype = st
+    L.osc_validate_sample.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(i64),
+                                      ctypes.POINTER(i64), vp]
+    L.osc_validate_sample.restype = st
     L.osc_reweight_layered.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_layer),
                                        i32, i32, vp, vp]
     L.osc_reweight_layered.restype = st
@@ -316,6 +319,16 @@ class Context:
         _check(load().osc_fill_pdf(self.handle, ctypes.byref(cs), int(set_index), ctypes.byref(b),
                                    int(precision), _ptr(hist_out), _ptr(p_out), _stream(stream)),
                "osc_fill_pdf")
+
+    def osc_validate_sample(self, sample: DeviceSample, stream=None):
+        """(events with a true energy that is not finite and > 0, events with
+        an invalid flag byte)."""
+        cs = sample.c_struct()
+        be, bf = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().osc_validate_sample(self.handle, ctypes.byref(cs), ctypes.byref(be),
+                                          ctypes.byref(bf), _stream(stream)),
+               "osc_validate_sample")
+        return be.value, bf.value
 
     def osc_reweight_layered(self, sample: DeviceSample, layers, set_index, p_out, stream=None):
         cs = sample.c_struct()

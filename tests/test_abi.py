@@ -37,7 +37,7 @@ def test_header_declares_the_entry_points():
                  "osc_batch_tune", "osc_server_create", "osc_server_submit", "osc_server_wait",
                  "osc_server_set_data", "osc_server_poll", "osc_reweight_layered",
                  "osc_fill_pdf_layered", "osc_template_create", "osc_template_copy",
-                 "osc_template_destroy", "osc_fill_pdf_bincentre"):
+                 "osc_template_destroy", "osc_fill_pdf_bincentre", "osc_validate_sample"):
         assert want in names
 
 

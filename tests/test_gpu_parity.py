@@ -444,3 +444,22 @@ def test_energy_scale_systematic(osc, ctx, e_scale):
     one = torch.ones(s.n, dtype=torch.float64, device="cuda")
     ctx.osc_fill_hist(one, one, ds.e_reco, 50, 0.0, 3.0, h, e_scale=e_scale)
     np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=52).astype(float))
+
+
+# --------------------------------------------------------------- domain check
+@pytest.mark.parametrize("n", [0, 1, 1000, 3_000_017])
+def test_validate_sample_counts(osc, ctx, n):
+    rng = np.random.default_rng(n + 3)
+    s = workload.make_sample(n, 5) if n else workload.make_sample(0, 5)
+    if n:
+        k = rng.choice(n, size=min(n, 40), replace=False)
+        s.e_true[k[:10]] = np.array([0.0, -1.0, np.nan, np.inf, -np.inf, 0.0, -0.0, 1e-300,
+                                     -5.0, np.nan])[:len(k[:10])]
+        s.flags[k[10:25]] = np.array([3, 7, 11, 12, 13, 14, 15, 32, 64, 128, 255, 35, 48, 19, 31],
+                                     np.uint8)[:len(k[10:25])]
+    ds = osc.DeviceSample.from_host(s)
+    be, bf = ctx.osc_validate_sample(ds)
+    e, f = s.e_true, s.flags.astype(int)
+    want_e = int(np.sum(~((e > 0) & np.isfinite(e))))
+    valid = (f < 32) & ((f & 3) < 3) & (((f >> 2) & 3) < 3)
+    assert (be, bf) == (want_e, int(np.sum(~valid)))
