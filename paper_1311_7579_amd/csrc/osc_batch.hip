@@ -76,11 +76,10 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
                                                            unsigned* __restrict__ queue)
 {
     extern __shared__ double hist[];
-    __shared__ Chan tab[kChannels];
-    __shared__ SinCos sct[64];
+    __shared__ TileTables tabs;
     const int lane = threadIdx.x;
     const int nbt = a.nbt;
-    if (!MIXED) load_sincos(sctab, sct, lane);   // read after the first barrier below
+    if (!MIXED) load_sincos(sctab, tabs, lane);   // read after the first barrier below
 
     int64_t item = a.dynamic ? take_item(queue, lane) : int64_t(blockIdx.x);
     while (item < a.n_items) {
@@ -99,10 +98,10 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
         for (int set = int(g) * a.sets_per_item; set < set_end; ++set) {
             const SetConsts& sc = sets[set];
             __syncthreads();   // the previous set's table and histogram are read
-            load_tab(sc, tab, lane);
+            load_tab(sc, tabs, lane);
             hist_zero(hist, lane, nbt);
             __syncthreads();
-            const ConstDensityProb<MIXED> prob{&sc, tab, sct, S.pc.kA, S.pc.kL};
+            const ConstDensityProb<MIXED> prob{&sc, &tabs, S.pc.kA, S.pc.kL};
             if (t.n == kTileEvents)
                 tile_events<kPdf, false, true>(prob, a.bc, hist, lane, t.n, t.e_true, t.flags,
                                                t.weight, t.e_reco, nullptr, nullptr);

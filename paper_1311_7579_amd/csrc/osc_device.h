@@ -60,9 +60,9 @@ __device__ __forceinline__ void phase_sincos(double x, const SinCos* __restrict_
 }
 
 // Copy the sin/cos anchors into LDS (the 64 lanes of a wave, one each).
-__device__ __forceinline__ void load_sincos(const SinCosTable& t, SinCos* lds, int lane)
+__device__ __forceinline__ void load_sincos(const SinCosTable& t, TileTables& T, int lane)
 {
-    if (lane < 64) lds[lane] = t.e[lane];
+    if (lane < 64) T.sct[lane] = t.e[lane];
 }
 
 // Mixed tier: the phase is reduced modulo 2 pi in FP64 (two-term
@@ -171,23 +171,22 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
 // exp(-i phi_0) drops out of |.|^2, so only the differences phi_k - phi_0
 // are formed.
 template <bool MIXED>
-__device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* tab,
-                                             const SinCos* sct, double kA, double kL, double E,
-                                             uint32_t f)
+__device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTables& T, double kA,
+                                             double kL, double E, uint32_t f)
 {
-    // flag byte: alpha bits 0-1, beta bits 2-3, antineutrino bit 4
-    const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
-    const uint32_t idx = min((f & 3u) + 3u * ((f >> 2) & 3u), uint32_t(kChannels - 1));
-    const uint32_t anti = (f << 27) & 0x80000000u;   // sign bit for A and the conjugation
-    const Chan c = tab[idx];
-    const double A = flip_sign(kA * E, anti);
-    const double dba = ((f & 3u) == ((f >> 2) & 3u)) ? 1.0 : 0.0;   // alpha = beta
+    // flag byte (alpha bits 0-1, beta bits 2-3, antineutrino bit 4) -> the
+    // channel entry (conjugated for antineutrinos) and the sign of A
+    const FlagInfo fl = T.flag[min(f, uint32_t(kFlagEntries - 1))];
+    const ChanL c = *reinterpret_cast<const ChanL*>(
+        reinterpret_cast<const unsigned char*>(T.ch) + fl.ch_off);
+    const double A = flip_sign(kA * E, fl.sign);
+    const double dba = c.dba;   // [alpha = beta]; NaN for an invalid flag byte
 
-    // amplitude inputs: M_ba and (M^2)_ba (conjugated for antineutrinos)
+    // amplitude inputs: M_ba and (M^2)_ba
     const double mre = fma(A, c.dee, c.m_re);
-    const double mim = flip_sign(c.m_im, anti);
+    const double mim = c.m_im;
     const double m2re = fma(A, fma(A, c.dee, c.g_re), c.m2_re);
-    const double m2im = flip_sign(fma(A, c.g_im, c.m2_im), anti);
+    const double m2im = fma(A, c.g_im, c.m2_im);
 
     // matter eigenvalues (FP64 in every tier)
     double l0, l1, l2;
@@ -207,8 +206,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
     double P;
     if constexpr (!MIXED) {
         double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, sct, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, sct, s2, c2);   // phi_2 - phi_0
+        phase_sincos(-d01 * ph, T.sct, s1, c1);   // phi_1 - phi_0
+        phase_sincos(-d02 * ph, T.sct, s2, c2);   // phi_2 - phi_0
         const double x0r = fma(v0, dba, fma(-u0, mre, m2re)) * iD0;
         const double x0i = fma(-u0, mim, m2im) * iD0;
         const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
@@ -239,8 +238,7 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
         const float si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
         P = double(sr * sr + si * si);
     }
-    // invalid flags give a quiet NaN (high word 0x7ff80000)
-    return __hiloint2double(valid ? __double2hiint(P) : 0x7ff80000, __double2loint(P));
+    return P;
 }
 
 // P of one event through one constant-density layer: the policy the tile
@@ -248,12 +246,11 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Chan* ta
 template <bool MIXED>
 struct ConstDensityProb {
     const SetConsts* sc;
-    const Chan* tab;
-    const SinCos* sct;
+    const TileTables* tabs;
     double kA, kL;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
-        return event_prob<MIXED>(*sc, tab, sct, kA, kL, E, f);
+        return event_prob<MIXED>(*sc, *tabs, kA, kL, E, f);
     }
 };
 
@@ -266,9 +263,8 @@ struct ConstDensityProb {
 // so v becomes a2 (M M v) + a1 (M v) + a0 v.  M is the flavour-basis mass
 // matrix of the layer (H0 + A e_e e_e^T, conjugated with A -> -A for
 // antineutrinos); its entries come from the channel table.
-__device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const Chan* tab,
-                                                     const SinCos* sct, const LayerPath& lp,
-                                                     double E, uint32_t f)
+__device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const TileTables& T,
+                                                     const LayerPath& lp, double E, uint32_t f)
 {
     const bool valid = (f < 32u) && ((kValidFlags >> (f & 31u)) & 1u);
     const uint32_t a = min(f & 3u, 2u), b = min((f >> 2) & 3u, 2u);
@@ -279,8 +275,8 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-            hr[i][j] = tab[3 * i + j].m_re;
-            hi[i][j] = flip_sign(tab[3 * i + j].m_im, anti);
+            hr[i][j] = T.ch[3 * i + j].m_re;
+            hi[i][j] = flip_sign(T.ch[3 * i + j].m_im, anti);
         }
     double vr[3] = {a == 0u ? 1.0 : 0.0, a == 1u ? 1.0 : 0.0, a == 2u ? 1.0 : 0.0};
     double vi[3] = {0.0, 0.0, 0.0};
@@ -294,8 +290,8 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
         const double invQ = recip(d01 * d02 * d12);
         const double ph = pc.kL * invE;
         double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, sct, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, sct, s2, c2);   // phi_2 - phi_0
+        phase_sincos(-d01 * ph, T.sct, s1, c1);   // phi_1 - phi_0
+        phase_sincos(-d02 * ph, T.sct, s2, c2);   // phi_2 - phi_0
         // c_k = exp(-i dphi_k) / D_k (c_0 real)
         const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
         const double k1r = c1 * iD1, k1i = -s1 * iD1;
@@ -348,12 +344,11 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
 // P of one event through a layered path (FP64).
 struct LayeredProb {
     const SetConsts* sc;
-    const Chan* tab;
-    const SinCos* sct;
+    const TileTables* tabs;
     const LayerPath* lp;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
-        return event_prob_layered(*sc, tab, sct, *lp, E, f);
+        return event_prob_layered(*sc, *tabs, *lp, E, f);
     }
 };
 
@@ -555,13 +550,39 @@ __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const
     return a;
 }
 
-// Copy the channel table of a parameter set into LDS (all lanes of the wave).
-__device__ __forceinline__ void load_tab(const SetConsts& sc, Chan* tab, int lane)
+// Build the channel and flag tables of a parameter set in LDS (lanes 0-31
+// of the block's first wave; the caller's barrier publishes them).
+__device__ __forceinline__ void load_tab(const SetConsts& sc, TileTables& T, int lane)
 {
-    constexpr int kWords = kChannels * int(sizeof(Chan) / sizeof(double));
-    const double* src = reinterpret_cast<const double*>(sc.ch);
-    double* dst = reinterpret_cast<double*>(tab);
-    for (int i = lane; i < kWords; i += kTileLanes) dst[i] = src[i];
+    if (lane < kLdsChannels) {
+        ChanL e;
+        if (lane < kInvalidChannel) {
+            const int k = lane % kChannels;
+            const Chan c = sc.ch[k];
+            const bool conj = lane >= kChannels;
+            e.m_re = c.m_re;
+            e.m_im = conj ? -c.m_im : c.m_im;
+            e.m2_re = c.m2_re;
+            e.m2_im = conj ? -c.m2_im : c.m2_im;
+            e.g_re = c.g_re;
+            e.g_im = conj ? -c.g_im : c.g_im;
+            e.dee = c.dee;
+            e.dba = (k % 3 == k / 3) ? 1.0 : 0.0;
+        } else {
+            e.m_re = e.m_im = e.m2_re = e.m2_im = e.g_re = e.g_im = e.dee = 0.0;
+            e.dba = __builtin_nan("");
+        }
+        T.ch[lane] = e;
+    }
+    if (lane < kFlagEntries) {
+        const uint32_t f = uint32_t(lane);
+        const bool valid = (kValidFlags >> f) & 1u;
+        const uint32_t anti = (f >> 4) & 1u;
+        const uint32_t entry =
+            valid ? (f & 3u) + 3u * ((f >> 2) & 3u) + anti * uint32_t(kChannels)
+                  : uint32_t(kInvalidChannel);
+        T.flag[lane] = FlagInfo{entry * uint32_t(sizeof(ChanL)), valid && anti ? 0x80000000u : 0u};
+    }
 }
 
 __device__ __forceinline__ void hist_zero(double* hist, int lane, int nbt)

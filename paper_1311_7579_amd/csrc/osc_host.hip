@@ -346,9 +346,9 @@ osc_status osc_create(osc_ctx** out, int device)
     osc_ctx* ctx = new (std::nothrow) osc_ctx();
     if (!ctx) return OSC_ERR_OUT_OF_MEMORY;
     ctx->device = device;
-    // per-lane histograms: (nbins + 2) x 64 lanes x 8 B of dynamic LDS,
-    // next to the 9-entry channel table
-    const size_t static_lds = osc::kChannels * sizeof(osc::Chan);
+    // per-wave histograms: (nbins + 2) x kHistLanes accumulators x 8 B of
+    // dynamic LDS, next to the static tables (channels, flags, sin/cos)
+    const size_t static_lds = sizeof(osc::TileTables);
     size_t lds = prop.sharedMemPerBlock > static_lds ? prop.sharedMemPerBlock - static_lds : 0;
     if (osc::set_kernel_attributes(lds) != hipSuccess) {
         // keep to the default 64 KiB per workgroup when the larger limit is refused

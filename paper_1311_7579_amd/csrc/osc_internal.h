@@ -139,4 +139,36 @@ struct BinConsts {
 // a bit mask over f.
 constexpr uint32_t kValidFlags = 0x07770777u;
 
+// Tables a per-event kernel keeps in LDS, built by each block from a
+// SetConsts and the SinCosTable:
+//  * ch: the channel table per (alpha, beta, antineutrino): entries
+//    3 beta + alpha for neutrinos, 9 + 3 beta + alpha for antineutrinos
+//    (complex conjugates: m_im, m2_im and g_im negated), each with
+//    dba = [alpha = beta]; entry 18 (invalid flag bytes) is zero with
+//    dba = NaN, so P comes out NaN;
+//  * flag: for each flag byte f < 32 the byte offset of its ch entry and
+//    the sign bit of A (set for antineutrinos); bytes >= 32 use entry 31,
+//    which is invalid;
+//  * sct: the phase sine/cosine anchors.
+// The per-event decode of a flag byte is then one min, one LDS read and one
+// XOR.
+struct ChanL {
+    double m_re, m_im;
+    double m2_re, m2_im;
+    double g_re, g_im;
+    double dee, dba;
+};
+constexpr int kLdsChannels = 2 * kChannels + 1;
+constexpr int kInvalidChannel = 2 * kChannels;
+constexpr int kFlagEntries = 32;
+struct FlagInfo {
+    uint32_t ch_off;   // byte offset into TileTables::ch
+    uint32_t sign;     // 0 or 0x80000000: the sign bit of A
+};
+struct TileTables {
+    ChanL ch[kLdsChannels];
+    FlagInfo flag[kFlagEntries];
+    SinCos sct[64];
+};
+
 }  // namespace osc

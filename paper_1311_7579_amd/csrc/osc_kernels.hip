@@ -38,21 +38,20 @@ void tile_kernel(
     double* __restrict__ partial)
 {
     extern __shared__ double hist[];
-    __shared__ Chan tab[kChannels];
-    __shared__ SinCos sct[64];
+    __shared__ TileTables tabs;
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int nbt = bc.nb + 2;
 
     if (MODE != kHist) {
-        load_tab(sc, tab, lane);
-        if (!MIXED) load_sincos(sctab, sct, lane);
+        load_tab(sc, tabs, lane);
+        if (!MIXED) load_sincos(sctab, tabs, lane);
     }
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
-    const ConstDensityProb<MIXED> prob{&sc, tab, sct, pc.kA, pc.kL};
+    const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, value, p_out);
     if (t.n == kTileEvents)
         tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
@@ -76,19 +75,18 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
                          double* __restrict__ p_out, double* __restrict__ partial)
 {
     extern __shared__ double hist[];
-    __shared__ Chan tab[kChannels];
-    __shared__ SinCos sct[64];
+    __shared__ TileTables tabs;
 
     const int lane = threadIdx.x;
     const int64_t tile = blockIdx.x;
     const int nbt = bc.nb + 2;
 
-    load_tab(sc, tab, lane);
-    load_sincos(sctab, sct, lane);
+    load_tab(sc, tabs, lane);
+    load_sincos(sctab, tabs, lane);
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
-    const LayeredProb prob{&sc, tab, sct, &lp};
+    const LayeredProb prob{&sc, &tabs, &lp};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, p_out);
     if (t.n == kTileEvents)
         tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,

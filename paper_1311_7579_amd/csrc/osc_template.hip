@@ -94,10 +94,9 @@ __global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, SinCosTa
                                                           PathConsts pc, TrueBins tb,
                                                           double* __restrict__ P)
 {
-    __shared__ Chan tab[kChannels];
-    __shared__ SinCos sct[64];
-    load_tab(sc, tab, threadIdx.x);
-    load_sincos(sctab, sct, threadIdx.x);
+    __shared__ TileTables tabs;
+    load_tab(sc, tabs, threadIdx.x);
+    load_sincos(sctab, tabs, threadIdx.x);
     __syncthreads();
     const int64_t k = int64_t(blockIdx.x) * 64 + threadIdx.x;
     if (k >= int64_t(kTemplateChannels) * tb.nt) return;
@@ -109,7 +108,7 @@ __global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, SinCosTa
         E = tb.lo + off;
     }
     const uint32_t f = (c % 3u) | (((c / 3u) % 3u) << 2) | ((c / 9u) << 4);
-    P[k] = event_prob<false>(sc, tab, sct, pc.kA, pc.kL, E, f);
+    P[k] = event_prob<false>(sc, tabs, pc.kA, pc.kL, E, f);
 }
 
 // hist[r] for one reconstructed bin per wave: lane l adds the terms

@@ -126,6 +126,28 @@ def test_invalid_flags_give_nan(osc, ctx):
     assert np.isfinite(got[ok]).all()
 
 
+def test_every_flag_byte(osc, ctx):
+    """All 256 flag byte values at 40 energies each, both tiers: the 18
+    valid channels against the oracle, every other byte NaN."""
+    E = np.tile(10 ** np.linspace(-1.2, 1.4, 40), 256)
+    f = np.repeat(np.arange(256, dtype=np.uint8), 40)
+    s = workload.Sample(e_true=E, flags=f, weight=np.ones(E.size), e_reco=E, L_km=1300.0,
+                        rho_gcc=3.0)
+    want = oracle.prob_batch(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, E, f)
+    bad = np.isnan(want)
+    assert bad.sum() == (256 - 18) * 40
+    got = gpu_reweight(osc, ctx, s)
+    np.testing.assert_array_equal(np.isnan(got), bad)
+    assert np.abs(got[~bad] - want[~bad]).max() <= P_TOL
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.empty(12, dtype=torch.float64, device="cuda")
+    p = torch.empty(E.size, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf(ds, 0, 10, 0.0, 30.0, h, p, precision=osc.OSC_FP32_MIXED)
+    pm = host(p)
+    np.testing.assert_array_equal(np.isnan(pm), bad)
+    assert np.abs(pm[~bad] - want[~bad]).max() <= MIXED_TOL
+
+
 def test_probabilities_bounded_and_unitary(osc, ctx):
     # sum over final flavours is 1 for every initial flavour
     n = 30_000
@@ -225,6 +247,25 @@ def test_fill_hist_max_nbins(osc, ctx):
     with pytest.raises(osc.OscError):
         ctx.osc_fill_hist(dev(v), dev(w), dev(x), nb + 1, 0.0, 10.0,
                           torch.empty(nb + 3, dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fill_pdf_max_nbins(osc, ctx, precision):
+    """The largest bin count the context reports runs the full per-event
+    kernel (histograms next to the static LDS tables)."""
+    nb = ctx.max_nbins
+    s = workload.make_sample(20_000, 8)
+    s.e_reco = np.random.default_rng(8).uniform(-0.5, 10.5, s.n)
+    prec = osc.OSC_FP64 if precision == "fp64" else osc.OSC_FP32_MIXED
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.empty(nb + 2, dtype=torch.float64, device="cuda")
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf(ds, 0, nb, 0.0, 10.0, h, p, precision=prec)
+    P = host(p)
+    want = oracle.prob_batch(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags)
+    assert np.abs(P - want).max() <= (P_TOL if precision == "fp64" else MIXED_TOL)
+    bins = oracle.bin_indices(s.e_reco, 0.0, 10.0, nb)
+    np.testing.assert_array_equal(host(h), oracle.hist_contract(s.weight * P, bins, nb + 2))
 
 
 def test_c2_fill_pdf_full_size(osc, ctx):
