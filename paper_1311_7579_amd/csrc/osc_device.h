@@ -101,18 +101,21 @@ __device__ __forceinline__ double recip_coarse(double y)
     return fma(r, fma(-y, r, 1.0), r);
 }
 
-// arccos on [-1, 1] in FP32 for the eigenvalue seeds: Abramowitz & Stegun
-// 4.4.45 on |x| (error <= 6.7e-5 rad; the FP64 refinement below absorbs
-// seed errors far larger than that) and acos(-x) = pi - acos(x).
-__device__ __forceinline__ float acos_seed(float x)
+// arccos(x) / (6 pi) on [-1, 1] in FP32 (the seed angle theta/3 in
+// revolutions for the hardware cosine): Abramowitz & Stegun 4.4.45 on |x|
+// (error <= 6.7e-5 rad; the FP64 refinement below absorbs seed errors far
+// larger than that) with its coefficients scaled by 1 / (6 pi), and
+// acos(-x) = pi - acos(x).
+__device__ __forceinline__ float acos_seed_rev(float x)
 {
+    constexpr float c = 0.053051647697298445f;   // 1 / (6 pi)
     const float ax = __builtin_fabsf(x);
-    float p = -0.0187293f;
-    p = __builtin_fmaf(p, ax, 0.0742610f);
-    p = __builtin_fmaf(p, ax, -0.2121144f);
-    p = __builtin_fmaf(p, ax, 1.5707288f);
+    float p = -0.0187293f * c;
+    p = __builtin_fmaf(p, ax, 0.0742610f * c);
+    p = __builtin_fmaf(p, ax, -0.2121144f * c);
+    p = __builtin_fmaf(p, ax, 1.5707288f * c);
     const float r = __builtin_amdgcn_sqrtf(1.0f - ax) * p;
-    return x < 0.0f ? 3.14159265358979f - r : r;
+    return x < 0.0f ? (1.0f / 6.0f) - r : r;
 }
 
 // Roots of f(x) = x^3 - tr x^2 + c1 x - det (three real roots: the matrix
@@ -132,7 +135,7 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
     float rf = 0.5f * qf * (rs * rs * rs);                      // q / (2 p^3/2)
     rf = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, rf));
     // theta in revolutions for the hardware cosine: acos(r) / (3 * 2 pi)
-    const float th = acos_seed(rf) * 0.053051647697298445f;
+    const float th = acos_seed_rev(rf);
     const double k = double((2.0f / 3.0f) * (pf * rs));
     const double t3 = tr * (1.0 / 3.0);
     double x0 = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
@@ -354,17 +357,19 @@ struct LayeredProb {
 
 // Bin of x: floor(fl(fl(x * scale - lo) / wb)) with under/overflow.  The
 // quotient is first formed as fl(x * scale - lo) * fl(1 / wb); that is
-// within 3 ulp of the correctly rounded quotient, so the floors agree unless
-// the product lies within 2^-40 of an integer (the bound for quotients below
-// 2^11).  Such lanes are flagged and redone with the correctly rounded
-// division; beyond 2^11 the bin is overflow (or underflow) either way.
+// within 3 u |q| (u = 2^-53) of the correctly rounded quotient q, so the
+// floors agree unless an integer lies within that distance.  Below
+// kFastBinLimit = 2^12 in magnitude the distance is under 1.5 * 2^-40;
+// lanes within 2^-38 of an integer are flagged and redone with the
+// correctly rounded division.  Beyond 2^12 the bin is overflow (or
+// underflow) either way, since no binning has that many bins.
 __device__ __forceinline__ double bin_floor_fast(double x, const BinConsts& bc, bool& edge)
 {
 #pragma clang fp contract(off)
     const double d = x * bc.scale - bc.lo;   // scaled energy, then the offset: two roundings
     const double q = d * bc.inv_wb;
     const double k = __builtin_floor(q);
-    edge = (__builtin_fabs((q - k) - 0.5) > 0.5 - 0x1p-40) && (__builtin_fabs(q) < 0x1p11);
+    edge = (__builtin_fabs((q - k) - 0.5) > 0.5 - 0x1p-38) && (__builtin_fabs(q) < kFastBinLimit);
     return k;
 }
 
@@ -422,7 +427,7 @@ struct EventIn {
 // Tile-relative 32-bit indices let every load use the scalar tile base plus
 // a 32-bit lane offset.
 template <int MODE, bool FULL>
-__device__ __forceinline__ EventIn load_event(int i, int n, const double* e_true,
+__device__ __forceinline__ EventIn load_event(uint32_t i, uint32_t n, const double* e_true,
                                               const uint8_t* flags, const double* weight,
                                               const double* e_reco, const double* value)
 {
@@ -440,8 +445,8 @@ __device__ __forceinline__ EventIn load_event(int i, int n, const double* e_true
 // dummy inputs), then stored, binned and accumulated in ascending m.
 template <int MODE, bool WRITE_P, bool FULL, class PROB>
 __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc, double* hist,
-                                           int lane, int i0, int n, const EventIn (&ev)[kGroup],
-                                           double* p_out)
+                                           int lane, uint32_t i0, uint32_t n,
+                                           const EventIn (&ev)[kGroup], double* p_out)
 {
     double P[kGroup], k[kGroup];
     bool edge[kGroup];
@@ -453,7 +458,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     if (WRITE_P) {
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-            const int i = i0 + j * kTileLanes;
+            const uint32_t i = i0 + j * kTileLanes;
             if (FULL || i < n) p_out[i] = P[j];
         }
     }
@@ -468,7 +473,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     }
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
-        const int i = i0 + j * kTileLanes;
+        const uint32_t i = i0 + j * kTileLanes;
         if (FULL || i < n) {
 #pragma clang fp contract(off)
             const double cval = ev[j].w * P[j];            // rounded, never fused
@@ -497,26 +502,27 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
 // group g + 1 are issued before group g is computed.
 template <int MODE, bool WRITE_P, bool FULL, class PROB>
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
-                                            int lane, int n, const double* e_true,
+                                            int lane, uint32_t n, const double* e_true,
                                             const uint8_t* flags, const double* weight,
                                             const double* e_reco, const double* value,
                                             double* p_out)
 {
     constexpr int kGroups = kLaneEvents / kGroup;
+    const uint32_t l = uint32_t(lane);
     EventIn ev[kGroups][kGroup];
 #pragma unroll
     for (int j = 0; j < kGroup; ++j)
-        ev[0][j] = load_event<MODE, FULL>(lane + j * kTileLanes, n, e_true, flags, weight,
-                                          e_reco, value);
+        ev[0][j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight, e_reco,
+                                          value);
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
         if (g + 1 < kGroups) {
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
-                ev[g + 1][j] = load_event<MODE, FULL>(lane + ((g + 1) * kGroup + j) * kTileLanes,
-                                                      n, e_true, flags, weight, e_reco, value);
+                ev[g + 1][j] = load_event<MODE, FULL>(l + ((g + 1) * kGroup + j) * kTileLanes, n,
+                                                      e_true, flags, weight, e_reco, value);
         }
-        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, lane + g * kGroup * kTileLanes, n,
+        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes, n,
                                         ev[g], p_out);
     }
 }
@@ -530,7 +536,7 @@ struct TileArrays {
     const double* e_reco;
     const double* value;
     double* p_out;
-    int n;
+    uint32_t n;
 };
 
 __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const double* e_true,
@@ -546,7 +552,7 @@ __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const
     a.e_reco = e_reco ? e_reco + t0 : nullptr;
     a.value = value ? value + t0 : nullptr;
     a.p_out = p_out ? p_out + t0 : nullptr;
-    a.n = int(min(n - t0, int64_t(kTileEvents)));
+    a.n = uint32_t(min(n - t0, int64_t(kTileEvents)));
     return a;
 }
 

@@ -356,7 +356,7 @@ osc_status osc_create(osc_ctx** out, int device)
         lds = std::min<size_t>(lds, 65536 - static_lds);
     }
     const size_t row = size_t(osc::kHistLanes) * sizeof(double);
-    ctx->max_nbins = int32_t(lds / row) - 2;
+    ctx->max_nbins = std::min<int32_t>(int32_t(lds / row) - 2, osc::kMaxBins);
     ctx->max_dyn_lds = lds;
     if (ctx->max_nbins < 1) {
         delete ctx;

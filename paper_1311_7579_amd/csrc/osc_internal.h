@@ -127,6 +127,11 @@ struct LayerPath {
     PathConsts layer[kMaxLayers];
 };
 
+// The fast bin index is exact for quotients below this magnitude, so no
+// binning may have more regular bins (under/overflow included).
+constexpr double kFastBinLimit = 4096.0;
+constexpr int32_t kMaxBins = 4094;
+
 struct BinConsts {
     double lo;
     double wb;      // (hi - lo) / nbins, computed on the host in FP64

@@ -208,7 +208,8 @@ def test_fill_hist_counts_exact(osc, ctx, nbins, lo, hi):
     np.testing.assert_array_equal(host(h), np.bincount(bins, minlength=nbins + 2).astype(float))
 
 
-@pytest.mark.parametrize("nbins,lo,hi", [(50, 0.0, 3.0), (37, 0.5, 9.5), (316, -1.0, 0.7)])
+@pytest.mark.parametrize("nbins,lo,hi", [(50, 0.0, 3.0), (37, 0.5, 9.5), (316, -1.0, 0.7),
+                                        (100_000, 0.0, 7.3), (100_000, -0.37, 0.91)])
 def test_fill_hist_bin_edges_exact(osc, ctx, nbins, lo, hi):
     """Values on every bin edge and on the three neighbouring doubles either
     side: bin indices (hence counts) must equal the FP64 quotient rule."""
