@@ -126,7 +126,15 @@ osc_status osc_validate_sample(osc_ctx* ctx, const osc_sample* sample, int64_t* 
 
 /* Sec. 2.1 (the paper's kernel): write P(alpha -> beta) of every event of
  * `sample` under parameter set `set` to p_out (device, n FP64 entries,
- * event order).  weight and e_reco are not read. */
+ * event order).  weight and e_reco are not read.
+ * Accuracy domain (all per-event entry points): P is within about 1e-12 of
+ * the exact value (plus 2^-53 |A| / (smallest eigenvalue distance) from
+ * the amplitude's own cancellation) for matter terms |A| = K_A Ye rho E up
+ * to about 1 eV^2 with mixing angles near the measured ones (Table 1:
+ * E rho Ye up to ~6500 GeV g/cm^3), and up to about 0.04 eV^2 for
+ * arbitrary angles.  Beyond that the FP32 seeds of the eigenvalue solver
+ * can no longer resolve the two roots that stay near the vacuum masses and
+ * P is not reliable. */
 osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         double* p_out, void* stream);
 

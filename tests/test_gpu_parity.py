@@ -105,6 +105,53 @@ def test_all_channels_random_parameters(osc, ctx, L, rho):
         ctx.osc_set_params([workload.TABLE1])
 
 
+def large_a_conditioning(p, s, flags):
+    """|A| / (smallest distance between eigenvalues of M) per event."""
+    m2 = np.array([0.0, p["dm2_21"], p["dm2_21"] + p["dm2_32"]])
+    anti = (flags >> 4) & 1
+    A = oracle.k_matter() * s.Ye * s.rho_gcc * s.e_true * np.where(anti == 1, -1.0, 1.0)
+    out = np.empty(s.n)
+    for a in (0, 1):
+        U = oracle.pmns(p, anti=bool(a))
+        H = (U * m2) @ U.conj().T
+        sel = anti == a
+        M = np.broadcast_to(H, (int(sel.sum()), 3, 3)).copy()
+        M[:, 0, 0] += A[sel]
+        lam = np.linalg.eigvalsh(M)
+        out[sel] = np.abs(A[sel]) / np.min(np.diff(lam, axis=1), axis=1)
+    return out
+
+
+def test_matter_term_domain(osc, ctx):
+    """Large matter terms within the solver's stated domain, mixed in the
+    same waves with ordinary energies: |A| up to 0.8 eV^2 (E up to ~1 TeV
+    through 13 g/cm^3) for Table 1 and sets around it, up to 0.03 eV^2 for
+    broad random sets (any angles, both orderings).  P against the oracle
+    within 1e-12 plus 64 u |A| / (smallest root distance) (u = 2^-53: both
+    amplitudes lose about u |A| / distance to cancellation)."""
+    n = 40_000
+    rng = np.random.default_rng(8)
+    ka = 1.526493e-4 * 0.5 * 13.0
+    cases = [((workload.TABLE1,) + tuple(workload.make_param_sets(3, 3)), 0.8),
+             (tuple(workload.make_random_physics_sets(4, 5)), 0.03)]
+    for sets, a_max in cases:
+        big = 10 ** rng.uniform(np.log10(0.01 * a_max / ka), np.log10(a_max / ka), n)
+        small = 10 ** rng.uniform(-0.5, 1.0, n)
+        E = np.where(rng.random(n) < 0.5, big, small)
+        f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), rng.random(n) < 0.5)
+        s = workload.Sample(e_true=E, flags=f, weight=np.ones(n), e_reco=E, L_km=2500.0,
+                            rho_gcc=13.0)
+        for p in sets:
+            ctx.osc_set_params([p])
+            try:
+                got = gpu_reweight(osc, ctx, s, 0)
+            finally:
+                ctx.osc_set_params([workload.TABLE1])
+            want = oracle.prob_batch(p, s.L_km, s.rho_gcc, s.Ye, E, f)
+            tol = 1e-12 + 64 * 2.0 ** -53 * large_a_conditioning(p, s, f)
+            assert np.all(np.abs(got - want) <= tol), (a_max, p)
+
+
 def test_paper_validation_protocol(osc, ctx):
     """Sec. 2.2: 1e7 energies uniform on (0, 30] GeV, CPU vs GPU residual
     of order 1e-12 (every channel, neutrinos and antineutrinos)."""
