@@ -201,25 +201,26 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
     const double invE = Q * R, invQ = E * R;
     const double ph = kL * invE;
     // numerator coefficients: N_k = (M^2)_ba - (l_j + l_l) M_ba + l_j l_l [a = b]
-    const double u0 = l1 + l2, v0 = l1 * l2;
+    // for k = 1, 2.  The projectors sum to the identity, so X0 = [a = b] -
+    // X1 - X2 and S' = [a = b] + (exp(-i dphi1) - 1) X1 + (exp(-i dphi2) - 1) X2;
+    // the projectors of a Hermitian matrix have entries of modulus <= 1, so
+    // forming cos - 1 costs nothing in absolute accuracy.
     const double u1 = l0 + l2, v1 = l0 * l2;
     const double u2 = l0 + l1, v2 = l0 * l1;
-    const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
+    const double iD1 = -d02 * invQ, iD2 = d01 * invQ;
 
     double P;
     if constexpr (!MIXED) {
         double s1, c1, s2, c2;
         phase_sincos(-d01 * ph, T.sct, s1, c1);   // phi_1 - phi_0
         phase_sincos(-d02 * ph, T.sct, s2, c2);   // phi_2 - phi_0
-        const double x0r = fma(v0, dba, fma(-u0, mre, m2re)) * iD0;
-        const double x0i = fma(-u0, mim, m2im) * iD0;
         const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
         const double x1i = fma(-u1, mim, m2im) * iD1;
         const double x2r = fma(v2, dba, fma(-u2, mre, m2re)) * iD2;
         const double x2i = fma(-u2, mim, m2im) * iD2;
-        // S' = X0 + exp(-i dphi1) X1 + exp(-i dphi2) X2
-        const double sr = x0r + c1 * x1r + s1 * x1i + c2 * x2r + s2 * x2i;
-        const double si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
+        const double e1 = c1 - 1.0, e2 = c2 - 1.0;
+        const double sr = dba + e1 * x1r + s1 * x1i + e2 * x2r + s2 * x2i;
+        const double si = e1 * x1i - s1 * x1r + e2 * x2i - s2 * x2r;
         P = sr * sr + si * si;
     } else {
         float s1, c1, s2, c2;
@@ -228,17 +229,16 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
         // amplitude assembly in FP32 from FP32-rounded inputs
         const float fmre = float(mre), fmim = float(mim), fm2re = float(m2re), fm2im = float(m2im);
         const float fdba = float(dba);
-        const float fu0 = float(u0), fu1 = float(u1), fu2 = float(u2);
-        const float fv0 = float(v0), fv1 = float(v1), fv2 = float(v2);
-        const float fi0 = float(iD0), fi1 = float(iD1), fi2 = float(iD2);
-        const float x0r = __builtin_fmaf(fv0, fdba, __builtin_fmaf(-fu0, fmre, fm2re)) * fi0;
-        const float x0i = __builtin_fmaf(-fu0, fmim, fm2im) * fi0;
+        const float fu1 = float(u1), fu2 = float(u2);
+        const float fv1 = float(v1), fv2 = float(v2);
+        const float fi1 = float(iD1), fi2 = float(iD2);
         const float x1r = __builtin_fmaf(fv1, fdba, __builtin_fmaf(-fu1, fmre, fm2re)) * fi1;
         const float x1i = __builtin_fmaf(-fu1, fmim, fm2im) * fi1;
         const float x2r = __builtin_fmaf(fv2, fdba, __builtin_fmaf(-fu2, fmre, fm2re)) * fi2;
         const float x2i = __builtin_fmaf(-fu2, fmim, fm2im) * fi2;
-        const float sr = x0r + c1 * x1r + s1 * x1i + c2 * x2r + s2 * x2i;
-        const float si = x0i + c1 * x1i - s1 * x1r + c2 * x2i - s2 * x2r;
+        const float e1 = c1 - 1.0f, e2 = c2 - 1.0f;
+        const float sr = fdba + e1 * x1r + s1 * x1i + e2 * x2r + s2 * x2i;
+        const float si = e1 * x1i - s1 * x1r + e2 * x2i - s2 * x2r;
         P = double(sr * sr + si * si);
     }
     return P;
