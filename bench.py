@@ -36,9 +36,9 @@ SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # (an FMA counts two): matter term and amplitude inputs 9, cubic
 # coefficients 14, trigonometric seeds (scaling in FP64) 6, one Halley and
 # one Newton step on two roots 75, third root 2, differences, 1/(E Q) and
-# the phase scale 17, projector coefficients 9, phase differences 2, two
-# sin/cos 74, projector numerators 24, amplitude sum 16, |S|^2 3, bin and
-# weighted add 6.
+# the phase scale 17, coefficients of the projectors X1 and X2 6, phase
+# differences 2, two sin/cos 74, numerators of X1 and X2 16, cos - 1 twice
+# and the amplitude sum 17, |S|^2 3, bin and weighted add 6.
 FLOPS_PER_EVENT = 247
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
@@ -55,8 +55,28 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
 COUNTER_TRAFFIC = {
     "fetch_kib": 122418.5, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
     "write_kib": 94322.6, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
+    # quarter-rate transcendentals among them, from the same run
+    "valu_per_event": 217.5, "trans_per_event": 8,
     "source_sha256": "9b8783a30c54691934904db4bdd3f656d91965caef311f261d73b0691c2a2c7d",
 }
+# VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
+# transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.
+VALU_SIMDS = 1024
+CLOCK_HZ = 2.4e9
+
+
+def valu_issue(kernel_ms):
+    """Fraction of the kernel's duration the SIMDs need just to issue its
+    VALU instructions (counter figures of the current sources, else None)."""
+    if kernel_sources_sha256() != COUNTER_TRAFFIC["source_sha256"]:
+        return None
+    per_event = COUNTER_TRAFFIC["valu_per_event"]
+    trans = COUNTER_TRAFFIC["trans_per_event"]
+    cycles = (per_event * 4 + trans * 12) * (N_EVENTS / 64) / VALU_SIMDS
+    need_ms = cycles / CLOCK_HZ * 1e3
+    return {"valu_insts_per_event": per_event, "transcendentals_per_event": trans,
+            "issue_ms_at_peak_clock": need_ms, "frac": need_ms / kernel_ms}
 
 
 def parse():
@@ -481,6 +501,7 @@ def main():
                                              if traffic else None)},
         "merge_kernel_ms": merge_avg_ms,
         "resident_waves_per_cu": waves_per_cu,
+        "valu_issue": valu_issue(kernel_ms),
     }
 
     result = {
