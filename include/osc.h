@@ -389,8 +389,9 @@ osc_status osc_server_request_bytes(const osc_server* server, int32_t sample, in
  * and A accumulators per bin of a tile.  Any pointer may be NULL. */
 void osc_reduction_layout(int32_t* tile_lanes, int32_t* lane_events, int32_t* accumulators);
 
-/* Largest nbins osc_fill_pdf accepts on this context's device (the
- * per-lane histograms live in LDS). */
+/* Largest nbins osc_fill_pdf accepts on this context's device: the
+ * per-wave histograms (nbins + 2 rows of 8 accumulators) live in LDS next
+ * to the static tables, and no binning exceeds 4094 bins. */
 int32_t osc_max_nbins(const osc_ctx* ctx);
 
 /* Resident waves per compute unit of the per-event kernel (one wave per

@@ -85,8 +85,8 @@ __host__ __device__ inline int64_t partial_index(int64_t tile, int bin, int nbt)
 //   (M^2)_ba  = m2 + A g + A^2 [a = b = e],  g = [b = e] H0_ea + H0_be [a = e]
 // Antineutrinos use the complex conjugates and the opposite sign of A.
 // dee = [a = b = e] is stored as 0.0 / 1.0 so that the kernel applies it
-// with FMAs.  (Seven doubles: the 9-entry table stays within 512 bytes of
-// LDS, the allocation granule, next to the histograms.)
+// with FMAs.  The kernels expand these 9 entries into the flag-indexed LDS
+// tables of TileTables (conjugated copies for antineutrinos, [a = b]).
 struct Chan {
     double m_re, m_im;
     double m2_re, m2_im;
