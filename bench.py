@@ -58,7 +58,7 @@ COUNTER_TRAFFIC = {
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
     "valu_per_event": 217.5, "trans_per_event": 8,
-    "source_sha256": "9b8783a30c54691934904db4bdd3f656d91965caef311f261d73b0691c2a2c7d",
+    "source_sha256": "52321d6ede6c0dad57d5d590e6c9c02e96ad7275ea1be52f4c7bf5fec410fc99",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.
