@@ -498,9 +498,13 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
 }
 
 // The kLaneEvents events of one lane of the tile whose arrays start at the
-// tile's first event (n = the tile's events), fully unrolled: the loads of
-// group g + 1 are issued before group g is computed.
-template <int MODE, bool WRITE_P, bool FULL, class PROB>
+// tile's first event (n = the tile's events); the loads of group g + 1 are
+// issued before group g is computed.  With ROLL the events run in a loop
+// that is not unrolled (the last group reloads itself): about 6 KB of code
+// instead of 60 KB and fewer live registers.  The callers choose it per
+// kernel from measurements: rolled for the FP64 kernels that write P and
+// for the FP64 batched kernel, fully unrolled for the FP32-mixed tier.
+template <int MODE, bool WRITE_P, bool FULL, bool ROLL, class PROB>
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
                                             int lane, uint32_t n, const double* e_true,
                                             const uint8_t* flags, const double* weight,
@@ -509,21 +513,41 @@ __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& b
 {
     constexpr int kGroups = kLaneEvents / kGroup;
     const uint32_t l = uint32_t(lane);
-    EventIn ev[kGroups][kGroup];
+    if constexpr (ROLL) {
+        EventIn cur[kGroup], nxt[kGroup];
 #pragma unroll
-    for (int j = 0; j < kGroup; ++j)
-        ev[0][j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight, e_reco,
-                                          value);
-#pragma unroll
-    for (int g = 0; g < kGroups; ++g) {
-        if (g + 1 < kGroups) {
+        for (int j = 0; j < kGroup; ++j)
+            cur[j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight, e_reco,
+                                            value);
+#pragma unroll 1
+        for (int g = 0; g < kGroups; ++g) {
+            const int gn = g + 1 < kGroups ? g + 1 : g;   // the last group reloads itself
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
-                ev[g + 1][j] = load_event<MODE, FULL>(l + ((g + 1) * kGroup + j) * kTileLanes, n,
-                                                      e_true, flags, weight, e_reco, value);
+                nxt[j] = load_event<MODE, FULL>(l + (gn * kGroup + j) * kTileLanes, n, e_true,
+                                                flags, weight, e_reco, value);
+            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes, n,
+                                            cur, p_out);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) cur[j] = nxt[j];
         }
-        tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes, n,
-                                        ev[g], p_out);
+    } else {
+        EventIn ev[kGroups][kGroup];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j)
+            ev[0][j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight,
+                                              e_reco, value);
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g) {
+            if (g + 1 < kGroups) {
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    ev[g + 1][j] = load_event<MODE, FULL>(l + ((g + 1) * kGroup + j) * kTileLanes,
+                                                          n, e_true, flags, weight, e_reco, value);
+            }
+            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes,
+                                            n, ev[g], p_out);
+        }
     }
 }
 

@@ -54,11 +54,13 @@ void tile_kernel(
     const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, value, p_out);
     if (t.n == kTileEvents)
-        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
-                                         t.e_reco, t.value, t.p_out);
+        tile_events<MODE, WRITE_P, true, !MIXED && WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
+                                                            t.flags, t.weight, t.e_reco,
+                                                            t.value, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
-                                          t.e_reco, t.value, t.p_out);
+        tile_events<MODE, WRITE_P, false, !MIXED && WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
+                                                             t.flags, t.weight, t.e_reco,
+                                                             t.value, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -89,11 +91,11 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
     const LayeredProb prob{&sc, &tabs, &lp};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, p_out);
     if (t.n == kTileEvents)
-        tile_events<MODE, WRITE_P, true>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
-                                         t.e_reco, nullptr, t.p_out);
+        tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                  t.weight, t.e_reco, nullptr, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false>(prob, bc, hist, lane, t.n, t.e_true, t.flags, t.weight,
-                                          t.e_reco, nullptr, t.p_out);
+        tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                   t.weight, t.e_reco, nullptr, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
