@@ -53,12 +53,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122177.0, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 94429.4, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122160.7, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82995.2, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
-    "valu_per_event": 216.9, "trans_per_event": 8,
-    "source_sha256": "621280ddcb0bb6b41ccc388ae7c7c5b985e9f87e89d0b0fe4e88113e3224cc71",
+    "valu_per_event": 217.1, "trans_per_event": 8,
+    "source_sha256": "dfe6a55652d294e8696577869787b3123008f8095fa7d8591b770a59acfcb52f",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.

@@ -553,6 +553,18 @@ __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& b
     }
 }
 
+// Tile of workgroup b of nb: workgroups are dispatched round-robin over the
+// 8 XCDs (each with its own L2), so XCD x = b mod 8 is given the contiguous
+// tile range that starts at x q + min(x, r) (q = nb / 8, r = nb mod 8); a
+// bijection of [0, nb).  Neighbouring tiles then write their per-bin
+// results into the same cache lines from one L2.
+constexpr int64_t kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / kXcds, r = nb % kXcds, x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // The arrays of one tile: the sample's arrays advanced to the tile's first
 // event (absent arrays stay null) and the tile's event count.
 struct TileArrays {

@@ -41,7 +41,7 @@ void tile_kernel(
     __shared__ TileTables tabs;
 
     const int lane = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int nbt = bc.nb + 2;
 
     if (MODE != kHist) {
@@ -80,7 +80,7 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
     __shared__ TileTables tabs;
 
     const int lane = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int nbt = bc.nb + 2;
 
     load_tab(sc, tabs, lane);
