@@ -33,13 +33,14 @@ BYTES_PER_EVENT = 33
 HBM_PEAK_GBS = 8000.0
 SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # Algorithmic FP64 flops per event of the formulation the kernel follows
-# (an FMA counts two): matter term and amplitude inputs 9, cubic
-# coefficients 14, trigonometric seeds (scaling in FP64) 6, one Halley and
-# one Newton step on two roots 75, third root 2, differences, 1/(E Q) and
-# the phase scale 17, coefficients of the projectors X1 and X2 6, phase
-# differences 2, two sin/cos 74, numerators of X1 and X2 16, cos - 1 twice
-# and the amplitude sum 17, |S|^2 3, bin and weighted add 6.
-FLOPS_PER_EVENT = 247
+# (an FMA counts two, a reciprocal estimate one): matter term and amplitude
+# inputs 9, cubic coefficients 12, trigonometric seeds (scaling in FP64) 6,
+# one Halley and one Newton step on two roots 72, third root 2,
+# differences, 1/(E Q) and the phase scale 18, coefficients of the
+# projectors X1 and X2 6, two sin and cos - 1 of the phase differences 54
+# (the phase products sit inside their reduction FMAs), numerators of X1
+# and X2 16, amplitude sum 15, |S|^2 3, bin and weighted add 6.
+FLOPS_PER_EVENT = 219
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -53,12 +54,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122160.7, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82995.2, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122154.7, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82914.9, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
-    "valu_per_event": 217.1, "trans_per_event": 8,
-    "source_sha256": "dfe6a55652d294e8696577869787b3123008f8095fa7d8591b770a59acfcb52f",
+    "valu_per_event": 203.3, "trans_per_event": 8,
+    "source_sha256": "b4cc152c8604435e700d49aeae8ebd8d480c93ef90f156d8ed12ce562582b371",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.

@@ -19,65 +19,65 @@ constexpr int kGroup = 1;
 static_assert(kLaneEvents % kGroup == 0, "the group size divides the events per lane");
 
 // ---------------------------------------------------------------------------
-// FP64 sine and cosine of a phase (|x| up to ~1e6 rad).
-// x = n pi/32 + r with a two-term Cody-Waite reduction (FMA form), |r| <=
-// pi/64; sin r and cos r from their Taylor series to r^9 and r^8
-// (truncation below 1e-19 on that interval); then the angle-addition
-// formulas with sin and cos of (n mod 64) pi/32 from a table in LDS.
+// FP64 sine and cosine - 1 of a phase given in units of pi/32 as the
+// product a b (|a b| < 2^50).  The nearest integer n to the exact product
+// comes out of one FMA against 1.5 * 2^52 (n lands in the low mantissa
+// bits), u = a b - n (|u| <= 1/2) out of a second one, so the reduction is
+// exact up to the final rounding of u.  With r = u pi/32 (|r| <= pi/64):
+//   sin r      = r + r^3 (P3 + P5 u^2 + P7 u^4)   (Taylor, scaled to u;
+//                truncation below 7e-18),
+//   cos r - 1  = u^2 (Q2 + Q4 u^2 + Q6 u^4)        (least-maximum absolute
+//                error fit on |u| <= 1/2, error below 8e-18),
+// and the angle-addition formulas with the anchor k = n mod 64 from LDS:
+//   sin = s_k + s_k (cos r - 1) + c_k sin r,
+//   cos - 1 = (c_k - 1) + c_k (cos r - 1) - s_k sin r.
 // ---------------------------------------------------------------------------
-constexpr double kInvStep = 10.185916357881301489;        // 32 / pi
-constexpr double kStepHi = 0.098174770424681034820;       // fl(pi / 32)
-constexpr double kStepLo = 3.827021247335479e-18;         // fl(pi / 32 - fl(pi / 32))
-
-// (-1)^k / (2k+1)!  and  (-1)^k / (2k)!
-constexpr double kS3 = -1.0 / 6.0;
-constexpr double kS5 = 1.0 / 120.0;
-constexpr double kS7 = -1.0 / 5040.0;
-constexpr double kS9 = 1.0 / 362880.0;
-constexpr double kC2 = -1.0 / 2.0;
-constexpr double kC4 = 1.0 / 24.0;
-constexpr double kC6 = -1.0 / 720.0;
-constexpr double kC8 = 1.0 / 40320.0;
+constexpr double kRoundMagic = 6755399441055744.0;        // 1.5 * 2^52
+constexpr double kStep = 0.09817477042468103;             // fl(pi / 32)
+constexpr double kP3 = -0.0001577060784927359;            // -(pi/32)^3 / 3!
+constexpr double kP5 = 7.600081085793214e-08;             //  (pi/32)^5 / 5!
+constexpr double kP7 = -1.7440893260086657e-11;           // -(pi/32)^7 / 7!
+constexpr double kQ2 = -0.0048191427739688;
+constexpr double kQ4 = 3.870689497756199e-06;
+constexpr double kQ6 = -1.2434575820615234e-09;
 
 __device__ __forceinline__ double flip_sign(double v, uint32_t sign_bit)
 {
     return __hiloint2double(__double2hiint(v) ^ int(sign_bit), __double2loint(v));
 }
 
-__device__ __forceinline__ void phase_sincos(double x, const SinCos* __restrict__ table,
-                                             double& sn, double& cs)
+__device__ __forceinline__ void phase_sincos(double a, double b, const SinCosL* __restrict__ table,
+                                             double& sn, double& cm1)
 {
-    const double n = __builtin_rint(x * kInvStep);
-    double r = fma(-n, kStepHi, x);
-    r = fma(-n, kStepLo, r);
-    const SinCos a = table[int(n) & 63];
-    const double z = r * r;
-    const double ps = fma(z, fma(z, fma(z, kS9, kS7), kS5), kS3);
-    const double s = fma(r * z, ps, r);
-    const double c = fma(z, fma(z, fma(z, fma(z, kC8, kC6), kC4), kC2), 1.0);
-    sn = fma(a.s, c, a.c * s);
-    cs = fma(a.c, c, -(a.s * s));
+    const double t = __builtin_fma(a, b, kRoundMagic);
+    const double n = t - kRoundMagic;
+    const double u = __builtin_fma(a, b, -n);
+    const SinCosL k = table[__double2loint(t) & 63];
+    const double z = u * u;
+    const double s = __builtin_fma(u * z, __builtin_fma(z, __builtin_fma(z, kP7, kP5), kP3), u * kStep);
+    const double cm = z * __builtin_fma(z, __builtin_fma(z, kQ6, kQ4), kQ2);
+    sn = __builtin_fma(k.s, cm, __builtin_fma(k.c, s, k.s));
+    cm1 = __builtin_fma(k.c, cm, __builtin_fma(-k.s, s, k.cm1));
 }
 
-// Copy the sin/cos anchors into LDS (the 64 lanes of a wave, one each).
+// Copy the sin/cos anchors into LDS (the 64 lanes of a wave, one each);
+// c - 1 is exact for c >= 1/2 and within half an ulp of 1 below.
 __device__ __forceinline__ void load_sincos(const SinCosTable& t, TileTables& T, int lane)
 {
-    if (lane < 64) T.sct[lane] = t.e[lane];
+    if (lane < 64) {
+        const SinCos e = t.e[lane];
+        T.sct[lane] = SinCosL{e.s, e.c, e.c - 1.0};
+    }
 }
 
-// Mixed tier: the phase is reduced modulo 2 pi in FP64 (two-term
-// Cody-Waite), the remainder in revolutions is rounded to FP32 and the FP32
+// Mixed tier: the phase (a b in units of pi/32, so a b / 64 in revolutions)
+// is reduced to |rev| <= 1/2 in FP64 as above, rounded to FP32, and the FP32
 // hardware sine and cosine (argument in revolutions) finish the job.
-constexpr double kInvTwoPi = 0.15915494309189533577;
-constexpr double kTwoPiHi = 6.283185307179586232;             // fl(2 pi)
-constexpr double kTwoPiLo = 2.4492935982947064e-16;           // fl(2 pi - fl(2 pi))
-
-__device__ __forceinline__ void phase_sincos_mixed(double x, float& sn, float& cs)
+__device__ __forceinline__ void phase_sincos_mixed(double a, double b_rev, float& sn, float& cs)
 {
-    const double n = __builtin_rint(x * kInvTwoPi);
-    double r = fma(-n, kTwoPiHi, x);
-    r = fma(-n, kTwoPiLo, r);
-    const float rev = float(r * kInvTwoPi);
+    const double t = __builtin_fma(a, b_rev, kRoundMagic);
+    const double n = t - kRoundMagic;
+    const float rev = float(__builtin_fma(a, b_rev, -n));
     sn = __builtin_amdgcn_sinf(rev);
     cs = __builtin_amdgcn_cosf(rev);
 }
@@ -118,21 +118,31 @@ __device__ __forceinline__ float acos_seed_rev(float x)
     return x < 0.0f ? (1.0f / 6.0f) - r : r;
 }
 
+// A value the compiler cannot see through, kept in an SGPR pair.  3.0 is
+// not an inline constant of the FP64 VALU; as a literal it only fits the
+// two-address v_fmac form, which costs a register copy whenever the
+// addend stays live.  From an SGPR the three-address v_fma takes it.
+__device__ __forceinline__ double sgpr_value(double v)
+{
+    asm("" : "+s"(v));
+    return v;
+}
+
 // Roots of f(x) = x^3 - tr x^2 + c1 x - det (three real roots: the matrix
 // is Hermitian).  Two roots are seeded in FP32 from the trigonometric
 // solution x = tr/3 + (2/3) sqrt(p) cos(theta - 2 pi k / 3),
-// theta = acos(q / (2 p^1.5)) / 3 (p = tr^2 - 3 c1, q = 2 tr^3 - 9 tr c1 +
-// 27 det), each refined in FP64 by one Halley and one Newton step on f; the
-// third root follows from the trace.  The two roots' divisions of each
-// step share one reciprocal: 1/a = b / (a b), 1/b = a / (a b).
-__device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
+// theta = acos(q / (2 p^1.5)) / 3 (p = tr^2 - 3 c1; qh = q / 2 with
+// q = 2 tr^3 - 9 tr c1 + 27 det is passed in), each refined in FP64 by one
+// Halley and one Newton step on f; the third root follows from the trace.  The two roots'
+// divisions of each step share one reciprocal: 1/a = b / (a b),
+// 1/b = a / (a b).
+__device__ __forceinline__ void cubic_roots(double tr, double c1, double det, double qh,
                                             double& l0, double& l1, double& l2)
 {
     const double p = fma(tr, tr, -3.0 * c1);
-    const double q = fma(tr, fma(2.0 * tr, tr, -9.0 * c1), 27.0 * det);
-    const float pf = float(p), qf = float(q);
+    const float pf = float(p), qf = float(qh);
     const float rs = __builtin_amdgcn_rsqf(pf);                 // p^-1/2
-    float rf = 0.5f * qf * (rs * rs * rs);                      // q / (2 p^3/2)
+    float rf = qf * (rs * rs * rs);                             // q / (2 p^3/2)
     rf = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, rf));
     // theta in revolutions for the hardware cosine: acos(r) / (3 * 2 pi)
     const float th = acos_seed_rev(rf);
@@ -141,14 +151,16 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
     double x0 = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
     double x1 = fma(k, double(__builtin_amdgcn_cosf(th - 0.33333333f)), t3);
     const double tr2 = 2.0 * tr;
+    const double three = sgpr_value(3.0);
     // Halley: x -= 2 f f' / (2 f'^2 - f f'')
     {
         const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
         const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
-        const double g0 = fma(x0, fma(3.0, x0, -tr2), c1);
-        const double g1 = fma(x1, fma(3.0, x1, -tr2), c1);
-        const double d0 = fma(g0, g0, -0.5 * f0 * fma(6.0, x0, -tr2));
-        const double d1 = fma(g1, g1, -0.5 * f1 * fma(6.0, x1, -tr2));
+        const double g0 = fma(x0, fma(three, x0, -tr2), c1);
+        const double g1 = fma(x1, fma(three, x1, -tr2), c1);
+        // -f f''/2 = f (tr - 3x)
+        const double d0 = fma(g0, g0, f0 * fma(-three, x0, tr));
+        const double d1 = fma(g1, g1, f1 * fma(-three, x1, tr));
         const double r = recip_coarse(d0 * d1);
         x0 -= (f0 * g0) * (d1 * r);
         x1 -= (f1 * g1) * (d0 * r);
@@ -157,8 +169,8 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det,
     {
         const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
         const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
-        const double g0 = fma(x0, fma(3.0, x0, -tr2), c1);
-        const double g1 = fma(x1, fma(3.0, x1, -tr2), c1);
+        const double g0 = fma(x0, fma(three, x0, -tr2), c1);
+        const double g1 = fma(x1, fma(three, x1, -tr2), c1);
         const double r = recip_coarse(g0 * g1);
         x0 -= f0 * (g1 * r);
         x1 -= f1 * (g0 * r);
@@ -193,13 +205,15 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
 
     // matter eigenvalues (FP64 in every tier)
     double l0, l1, l2;
-    cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA, l0, l1, l2);
+    cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA,
+                fma(fma(A + sc.QH2, A, sc.QH1), A, sc.QH0), l0, l1, l2);
 
     const double d01 = l0 - l1, d02 = l0 - l2, d12 = l1 - l2;
     const double Q = d01 * d02 * d12;
     const double R = recip(E * Q);
     const double invE = Q * R, invQ = E * R;
-    const double ph = kL * invE;
+    // phase per eV^2 in units of pi/32 (FP64 tier) or of 2 pi (mixed tier)
+    const double ph = (MIXED ? kL * (1.0 / 64.0) : kL) * invE;
     // numerator coefficients: N_k = (M^2)_ba - (l_j + l_l) M_ba + l_j l_l [a = b]
     // for k = 1, 2.  The projectors sum to the identity, so X0 = [a = b] -
     // X1 - X2 and S' = [a = b] + (exp(-i dphi1) - 1) X1 + (exp(-i dphi2) - 1) X2;
@@ -211,21 +225,20 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
 
     double P;
     if constexpr (!MIXED) {
-        double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, T.sct, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, T.sct, s2, c2);   // phi_2 - phi_0
+        double s1, e1, s2, e2;                        // sin and cos - 1
+        phase_sincos(-d01, ph, T.sct, s1, e1);        // phi_1 - phi_0
+        phase_sincos(-d02, ph, T.sct, s2, e2);        // phi_2 - phi_0
         const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
         const double x1i = fma(-u1, mim, m2im) * iD1;
         const double x2r = fma(v2, dba, fma(-u2, mre, m2re)) * iD2;
         const double x2i = fma(-u2, mim, m2im) * iD2;
-        const double e1 = c1 - 1.0, e2 = c2 - 1.0;
         const double sr = dba + e1 * x1r + s1 * x1i + e2 * x2r + s2 * x2i;
         const double si = e1 * x1i - s1 * x1r + e2 * x2i - s2 * x2r;
         P = sr * sr + si * si;
     } else {
         float s1, c1, s2, c2;
-        phase_sincos_mixed(-d01 * ph, s1, c1);
-        phase_sincos_mixed(-d02 * ph, s2, c2);
+        phase_sincos_mixed(-d01, ph, s1, c1);
+        phase_sincos_mixed(-d02, ph, s2, c2);
         // amplitude assembly in FP32 from FP32-rounded inputs
         const float fmre = float(mre), fmim = float(mim), fm2re = float(m2re), fm2im = float(m2im);
         const float fdba = float(dba);
@@ -288,13 +301,16 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
         const PathConsts pc = lp.layer[layer];
         const double A = flip_sign(pc.kA * E, anti);
         double l0, l1, l2;
-        cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA, l0, l1, l2);
+        cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA,
+                    fma(fma(A + sc.QH2, A, sc.QH1), A, sc.QH0), l0, l1, l2);
         const double d01 = l0 - l1, d02 = l0 - l2, d12 = l1 - l2;
         const double invQ = recip(d01 * d02 * d12);
         const double ph = pc.kL * invE;
         double s1, c1, s2, c2;
-        phase_sincos(-d01 * ph, T.sct, s1, c1);   // phi_1 - phi_0
-        phase_sincos(-d02 * ph, T.sct, s2, c2);   // phi_2 - phi_0
+        phase_sincos(-d01, ph, T.sct, s1, c1);   // phi_1 - phi_0: sin, cos - 1
+        phase_sincos(-d02, ph, T.sct, s2, c2);   // phi_2 - phi_0
+        c1 += 1.0;
+        c2 += 1.0;
         // c_k = exp(-i dphi_k) / D_k (c_0 real)
         const double iD0 = d12 * invQ, iD1 = -d02 * invQ, iD2 = d01 * invQ;
         const double k1r = c1 * iD1, k1i = -s1 * iD1;

@@ -23,8 +23,15 @@ constexpr double kHbarcEvM = 197.3269804e-9;
 constexpr double kAvogadro = 6.02214076e23;
 constexpr double kFermiGeV = 1.1663787e-5;
 
-// phase m^2 L / 2E in natural units per (eV^2 km / GeV)
-double phase_constant() { return 1.0e3 / kHbarcEvM / (2.0 * 1.0e9); }
+// The phase m^2 L / 2E in natural units per (eV^2 / GeV) over L_km
+// kilometres, in units of pi/32 (the form the kernels take), rounded once
+// from extended precision.
+double phase_steps(double L_km)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    const long double k = 1.0e3L / static_cast<long double>(kHbarcEvM) / 2.0e9L;
+    return static_cast<double>(k * static_cast<long double>(L_km) * (32.0L / pi));
+}
 
 // 2 sqrt(2) G_F N_e E per (g/cm^3 * GeV * Ye), in eV^2
 double matter_constant()
@@ -96,6 +103,10 @@ osc::SetConsts osc::host::set_consts(const osc_params& p)
     sc.C0 = dm21 * dm31;                        // sum of principal 2x2 minors of H
     sc.CA = H[1][1].real() + H[2][2].real();    // d c1 / dA
     sc.DA = dm21 * dm31 * std::norm(U[0][0]);   // d det / dA = cofactor_ee(H)
+    // q/2 = tr^3 - 4.5 tr c1 + 13.5 det as a cubic in A
+    sc.QH2 = 3.0 * sc.T0 - 4.5 * sc.CA;
+    sc.QH1 = 3.0 * sc.T0 * sc.T0 - 4.5 * (sc.C0 + sc.T0 * sc.CA) + 13.5 * sc.DA;
+    sc.QH0 = sc.T0 * (sc.T0 * sc.T0 - 4.5 * sc.C0);
     for (int b = 0; b < 3; ++b)
         for (int a = 0; a < 3; ++a) {
             cplx g = 0.0;
@@ -241,7 +252,7 @@ bool osc::host::binning_ok(const osc_ctx* ctx, const osc_binning* b)
 
 osc::PathConsts osc::host::path_consts(const osc_sample* s)
 {
-    return osc::PathConsts{matter_constant() * s->Ye * s->rho_gcc, phase_constant() * s->L_km};
+    return osc::PathConsts{matter_constant() * s->Ye * s->rho_gcc, phase_steps(s->L_km)};
 }
 
 osc::BinConsts osc::host::bin_consts(const osc_binning* b)
@@ -466,7 +477,7 @@ osc::LayerPath layer_path(const osc_layer* layers, int32_t n_layers)
     lp.n = n_layers;
     for (int32_t j = 0; j < n_layers; ++j)
         lp.layer[j] = osc::PathConsts{matter_constant() * layers[j].Ye * layers[j].rho_gcc,
-                                      phase_constant() * layers[j].L_km};
+                                      phase_steps(layers[j].L_km)};
     return lp;
 }
 

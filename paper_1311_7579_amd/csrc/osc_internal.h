@@ -99,8 +99,11 @@ constexpr int kChannels = 9;   // index 3 beta + alpha
 // Parameter-only quantities of one oscillation parameter set.
 // Characteristic polynomial of M: x^3 - tr x^2 + c1 x - det with
 //   tr = T0 + A,  c1 = C0 + A CA,  det = A DA.
+// The trigonometric seed of its roots uses q/2 with q = 2 tr^3 - 9 tr c1 +
+// 27 det, expanded in A as q/2 = ((A + QH2) A + QH1) A + QH0.
 struct SetConsts {
     double T0, C0, CA, DA;
+    double QH0, QH1, QH2;
     Chan ch[kChannels];
 };
 
@@ -112,11 +115,17 @@ struct SinCos {
 struct SinCosTable {
     SinCos e[64];
 };
+// The LDS form of an anchor adds cm1 = c - 1, so that cos(phase) - 1 is
+// formed without cancellation.
+struct SinCosL {
+    double s, c, cm1;
+};
 
 // Path constants of one sample.
 struct PathConsts {
     double kA;   // matter term per GeV: A = +-kA * E (eV^2)
-    double kL;   // phase per eV^2 per 1/GeV: phase = kL * lambda / E
+    double kL;   // phase per eV^2 per 1/GeV in units of pi/32:
+                 // phase = (pi/32) * kL * lambda / E
 };
 
 // A path of piecewise-constant density: layers in the order the neutrino
@@ -154,7 +163,9 @@ constexpr uint32_t kValidFlags = 0x07770777u;
 //  * flag: for each flag byte f < 32 the byte offset of its ch entry and
 //    the sign bit of A (set for antineutrinos); bytes >= 32 use entry 31,
 //    which is invalid;
-//  * sct: the phase sine/cosine anchors.
+//  * sct: the phase sine/cosine anchors (24 B each: the table grows the
+//    per-wave LDS by 512 B, which still leaves room for the six waves per
+//    SIMD of a 50-bin histogram).
 // The per-event decode of a flag byte is then one min, one LDS read and one
 // XOR.
 struct ChanL {
@@ -173,7 +184,7 @@ struct FlagInfo {
 struct TileTables {
     ChanL ch[kLdsChannels];
     FlagInfo flag[kFlagEntries];
-    SinCos sct[64];
+    SinCosL sct[64];
 };
 
 }  // namespace osc
