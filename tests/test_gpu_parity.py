@@ -105,21 +105,58 @@ def test_all_channels_random_parameters(osc, ctx, L, rho):
         ctx.osc_set_params([workload.TABLE1])
 
 
-def large_a_conditioning(p, s, flags):
-    """|A| / (smallest distance between eigenvalues of M) per event."""
+@pytest.mark.parametrize("rho", [0.0, 5.5])
+def test_large_phases(osc, ctx, rho):
+    """Phases up to ~5e4 rad (12742 km, E down to 2 MeV).  The phase
+    reduction is exact, so what is left beyond 1e-12 is the FP64 rounding of
+    the phase on each side: a few ulp of the eigenvalues, which the
+    characteristic polynomial amplifies by (largest / smallest eigenvalue
+    distance), times the phase per eV^2."""
+    sets = [workload.TABLE1] + workload.make_random_physics_sets(3, 41)
+    ctx.osc_set_params(sets)
+    try:
+        s = workload.make_uniform_energy_sample(200_000, 43, e_max=0.05, e_min=0.002)
+        s.L_km, s.rho_gcc = 12742.0, rho
+        for k, p in enumerate(sets):
+            lam = eigenvalues(p, s, s.flags)
+            gap = np.min(np.diff(lam, axis=1), axis=1)
+            spread = lam[:, 2] - lam[:, 0]
+            phase = oracle.k_phase() * spread * s.L_km / s.e_true   # largest phase difference
+            got = gpu_reweight(osc, ctx, s, k)
+            want = oracle.prob_batch(p, s.L_km, rho, s.Ye, s.e_true, s.flags)
+            # an independent LAPACK route (eigh, then exp) stays within 0.04 of this bound
+            tol = 1e-12 + 4 * 2.0 ** -53 * phase * (1.0 + spread / gap)
+            assert float(phase.max()) > 3e4
+            assert np.all(np.abs(got - want) <= tol), (k, float(np.abs(got - want).max()))
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
+
+
+def matter_term(s, flags):
+    anti = (flags >> 4) & 1
+    return oracle.k_matter() * s.Ye * s.rho_gcc * s.e_true * np.where(anti == 1, -1.0, 1.0)
+
+
+def eigenvalues(p, s, flags):
+    """Ascending eigenvalues of M = H0 + A e_e e_e^T per event (LAPACK)."""
     m2 = np.array([0.0, p["dm2_21"], p["dm2_21"] + p["dm2_32"]])
     anti = (flags >> 4) & 1
-    A = oracle.k_matter() * s.Ye * s.rho_gcc * s.e_true * np.where(anti == 1, -1.0, 1.0)
-    out = np.empty(s.n)
+    A = matter_term(s, flags)
+    out = np.empty((s.n, 3))
     for a in (0, 1):
         U = oracle.pmns(p, anti=bool(a))
         H = (U * m2) @ U.conj().T
         sel = anti == a
         M = np.broadcast_to(H, (int(sel.sum()), 3, 3)).copy()
         M[:, 0, 0] += A[sel]
-        lam = np.linalg.eigvalsh(M)
-        out[sel] = np.abs(A[sel]) / np.min(np.diff(lam, axis=1), axis=1)
+        out[sel] = np.linalg.eigvalsh(M)
     return out
+
+
+def large_a_conditioning(p, s, flags):
+    """|A| / (smallest distance between eigenvalues of M) per event."""
+    lam = eigenvalues(p, s, flags)
+    return np.abs(matter_term(s, flags)) / np.min(np.diff(lam, axis=1), axis=1)
 
 
 def test_matter_term_domain(osc, ctx):
