@@ -59,7 +59,7 @@ COUNTER_TRAFFIC = {
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
     "valu_per_event": 203.3, "trans_per_event": 8,
-    "source_sha256": "b4cc152c8604435e700d49aeae8ebd8d480c93ef90f156d8ed12ce562582b371",
+    "source_sha256": "10f51273b8e68df7a866bf9dc987e8ea9f2a67940fa8cd45177c4c9a64f7e792",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.

@@ -42,7 +42,9 @@ typedef enum {
 
 typedef enum {
     OSC_FP64 = 0,        /* every step in FP64 (the paper's precision, Sec. 2.1) */
-    OSC_FP32_MIXED = 1   /* FP64 eigenvalues and phases, FP32 amplitude assembly  */
+    OSC_FP32_MIXED = 1   /* FP64 eigenvalues and phases, FP32 amplitude assembly
+                            (eigenvalues refined until within ~1e-11 of their
+                            smallest distance, not to the last bit)            */
 } osc_precision;
 
 /* Opaque context bound to one device: holds the parameter sets and the

@@ -136,6 +136,14 @@ __device__ __forceinline__ double sgpr_value(double v)
 // Halley and one Newton step on f; the third root follows from the trace.  The two roots'
 // divisions of each step share one reciprocal: 1/a = b / (a b),
 // 1/b = a / (a b).
+// HALLEY_ONLY (the FP32-mixed tier): a wave skips the Newton step when
+// every lane's Halley corrections were at most 2^-12 of its smallest root
+// distance.  Halley converges cubically, so the roots are then within about
+// (2^-12)^3 ~ 1.5e-11 of that distance, far below what the FP32 amplitude
+// assembly resolves, and the phases stay within ~1e-8 rad up to 1e3 rad.
+constexpr double kHalleyOnly = 0x1p-12;
+
+template <bool HALLEY_ONLY = false>
 __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, double qh,
                                             double& l0, double& l1, double& l2)
 {
@@ -162,8 +170,26 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
         const double d0 = fma(g0, g0, f0 * fma(-three, x0, tr));
         const double d1 = fma(g1, g1, f1 * fma(-three, x1, tr));
         const double r = recip_coarse(d0 * d1);
-        x0 -= (f0 * g0) * (d1 * r);
-        x1 -= (f1 * g1) * (d0 * r);
+        if constexpr (!HALLEY_ONLY) {
+            x0 -= (f0 * g0) * (d1 * r);
+            x1 -= (f1 * g1) * (d0 * r);
+        } else {
+            const double h0 = (f0 * g0) * (d1 * r), h1 = (f1 * g1) * (d0 * r);
+            x0 -= h0;
+            x1 -= h1;
+            // x0 > x1 > x2 = tr - x0 - x1: the smallest root distance is
+            // x0 - x1 or x1 - x2 = 2 x1 + x0 - tr
+            const double dmin = __builtin_fmin(__builtin_fabs(x0 - x1),
+                                               __builtin_fabs(fma(2.0, x1, x0) - tr));
+            const bool done = __builtin_fmax(__builtin_fabs(h0), __builtin_fabs(h1)) <=
+                              kHalleyOnly * dmin;
+            if (__all(done)) {
+                l0 = x0;
+                l1 = x1;
+                l2 = (tr - l0) - l1;
+                return;
+            }
+        }
     }
     // Newton: x -= f / f'
     {
@@ -205,8 +231,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
 
     // matter eigenvalues (FP64 in every tier)
     double l0, l1, l2;
-    cubic_roots(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA,
-                fma(fma(A + sc.QH2, A, sc.QH1), A, sc.QH0), l0, l1, l2);
+    cubic_roots<MIXED>(sc.T0 + A, fma(A, sc.CA, sc.C0), A * sc.DA,
+                       fma(fma(A + sc.QH2, A, sc.QH1), A, sc.QH0), l0, l1, l2);
 
     const double d01 = l0 - l1, d02 = l0 - l2, d12 = l1 - l2;
     const double Q = d01 * d02 * d12;
