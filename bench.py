@@ -54,8 +54,8 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122154.7, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82914.9, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122173.2, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82906.1, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
     "valu_per_event": 203.3, "trans_per_event": 8,
