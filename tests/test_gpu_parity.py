@@ -189,6 +189,40 @@ def test_matter_term_domain(osc, ctx):
             assert np.all(np.abs(got - want) <= tol), (a_max, p)
 
 
+def test_mixed_tier_matter_term_domain(osc, ctx):
+    """The FP32-mixed tier on the same large-|A| inputs: waves whose Halley
+    corrections are not small relative to the root distance must still
+    take the Newton step, so P stays within the tier's tolerance plus the
+    FP32 share of the amplitude's cancellation (64 * 2^-24 |A| / distance);
+    roots left at the Halley step there would be off by ~1e-2 of the
+    distance."""
+    n = 40_000
+    rng = np.random.default_rng(9)
+    ka = 1.526493e-4 * 0.5 * 13.0
+    cases = [((workload.TABLE1,) + tuple(workload.make_param_sets(2, 3)), 0.8),
+             (tuple(workload.make_random_physics_sets(3, 5)), 0.03)]
+    for sets, a_max in cases:
+        big = 10 ** rng.uniform(np.log10(0.01 * a_max / ka), np.log10(a_max / ka), n)
+        small = 10 ** rng.uniform(-0.5, 1.0, n)
+        E = np.where(rng.random(n) < 0.5, big, small)
+        f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), rng.random(n) < 0.5)
+        s = workload.Sample(e_true=E, flags=f, weight=np.ones(n), e_reco=E, L_km=2500.0,
+                            rho_gcc=13.0)
+        ds = osc.DeviceSample.from_host(s)
+        h = torch.empty(52, dtype=torch.float64, device="cuda")
+        pm = torch.empty(n, dtype=torch.float64, device="cuda")
+        for p in sets:
+            ctx.osc_set_params([p])
+            try:
+                ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, pm, precision=osc.OSC_FP32_MIXED)
+                got = host(pm)
+            finally:
+                ctx.osc_set_params([workload.TABLE1])
+            want = oracle.prob_batch(p, s.L_km, s.rho_gcc, s.Ye, E, f)
+            tol = MIXED_TOL + 64 * 2.0 ** -24 * large_a_conditioning(p, s, f)
+            assert np.all(np.abs(got - want) <= tol), (a_max, p, float(np.abs(got - want).max()))
+
+
 def test_paper_validation_protocol(osc, ctx):
     """Sec. 2.2: 1e7 energies uniform on (0, 30] GeV, CPU vs GPU residual
     of order 1e-12 (every channel, neutrinos and antineutrinos)."""
