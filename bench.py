@@ -54,12 +54,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122173.2, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82906.1, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122167.8, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82936.3, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
     "valu_per_event": 203.3, "trans_per_event": 8,
-    "source_sha256": "10f51273b8e68df7a866bf9dc987e8ea9f2a67940fa8cd45177c4c9a64f7e792",
+    "source_sha256": "32dbda097c825baabde95a376aa882ebbc6294780cf9b5e8ae78fdb9ab5681ba",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.

@@ -546,8 +546,9 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
 // issued before group g is computed.  With ROLL the events run in a loop
 // that is not unrolled (the last group reloads itself): about 6 KB of code
 // instead of 60 KB and fewer live registers.  The callers choose it per
-// kernel from measurements: rolled for the FP64 kernels that write P and
-// for the FP64 batched kernel, fully unrolled for the FP32-mixed tier.
+// kernel from measurements: rolled for the kernels that write P (both
+// tiers) and for the batched kernel, fully unrolled for the kernels that
+// write no P.
 template <int MODE, bool WRITE_P, bool FULL, bool ROLL, class PROB>
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
                                             int lane, uint32_t n, const double* e_true,

@@ -54,11 +54,11 @@ void tile_kernel(
     const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, value, p_out);
     if (t.n == kTileEvents)
-        tile_events<MODE, WRITE_P, true, !MIXED && WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
+        tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
                                                             t.flags, t.weight, t.e_reco,
                                                             t.value, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false, !MIXED && WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
+        tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
                                                              t.flags, t.weight, t.e_reco,
                                                              t.value, t.p_out);
 
