@@ -82,15 +82,14 @@ __device__ __forceinline__ void phase_sincos_mixed(double a, double b_rev, float
     cs = __builtin_amdgcn_cosf(rev);
 }
 
-// 1/y to within a few ulp: hardware reciprocal estimate + two
-// Newton-Raphson corrections (y normal, not huge).
+// 1/y to within a few ulp: hardware reciprocal estimate r (relative error
+// e ~ 3e-7) and one third-order correction r (1 + e + e^2), e = 1 - y r,
+// which leaves ~e^3 (y normal, not huge).
 __device__ __forceinline__ double recip(double y)
 {
-    double r = __builtin_amdgcn_rcp(y);
-    double e = fma(-y, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-y, r, 1.0);
-    return fma(r, e, r);
+    const double r = __builtin_amdgcn_rcp(y);
+    const double e = fma(-y, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 
 // 1/y with one Newton-Raphson correction (relative error ~1e-13): enough
@@ -435,11 +434,13 @@ __device__ __forceinline__ int lds_row_of_output(int r, int nb)
 }
 
 // Histogram accumulator slot: bin-major rows of kHistLanes accumulators,
-// the accumulator index XOR-swizzled by the bin so that both the per-lane
+// the accumulator index XOR-swizzled by the row so that both the per-lane
 // accumulation and the per-bin transposed reads spread over the LDS banks.
-__device__ __forceinline__ int hslot(int bin, int acc)
+// The swizzle uses row - 1 (the floor value k of the row), so that the
+// row's +1 becomes a constant offset of the LDS instruction.
+__device__ __forceinline__ int hslot(int row, int acc)
 {
-    return bin * kHistLanes + (acc ^ (bin & (kHistLanes - 1) & 31));
+    return row * kHistLanes + (acc ^ ((row - 1) & (kHistLanes - 1)));
 }
 
 // complete binary tree over the kHistLanes accumulators of one bin
