@@ -36,11 +36,11 @@ SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # (an FMA counts two, a reciprocal estimate one): matter term and amplitude
 # inputs 9, cubic coefficients 12, trigonometric seeds (scaling in FP64) 6,
 # one Halley and one Newton step on two roots 72, third root 2,
-# differences, 1/(E Q) and the phase scale 18, coefficients of the
+# differences, 1/(E Q) and the phase scale 16, coefficients of the
 # projectors X1 and X2 6, two sin and cos - 1 of the phase differences 54
 # (the phase products sit inside their reduction FMAs), numerators of X1
 # and X2 16, amplitude sum 15, |S|^2 3, bin and weighted add 6.
-FLOPS_PER_EVENT = 219
+FLOPS_PER_EVENT = 217
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -54,12 +54,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122167.8, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82936.3, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122157.2, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82871.3, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
-    "valu_per_event": 203.3, "trans_per_event": 8,
-    "source_sha256": "32dbda097c825baabde95a376aa882ebbc6294780cf9b5e8ae78fdb9ab5681ba",
+    "valu_per_event": 201.3, "trans_per_event": 8,
+    "source_sha256": "13d0cdc5b67e94085fdd7a6d5a123a06b4ad06e12000ec0ffec0d3113d845cde",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.
