@@ -103,11 +103,11 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
             __syncthreads();
             const ConstDensityProb<MIXED> prob{&sc, &tabs, S.pc.kA, S.pc.kL};
             if (t.n == kTileEvents)
-                tile_events<kPdf, false, true, true>(prob, a.bc, hist, lane, t.n, t.e_true,
+                tile_events<kPdf, false, true, true, false>(prob, a.bc, hist, lane, t.n, t.e_true,
                                                        t.flags, t.weight, t.e_reco, nullptr,
                                                        nullptr);
             else
-                tile_events<kPdf, false, false, true>(prob, a.bc, hist, lane, t.n, t.e_true,
+                tile_events<kPdf, false, false, true, false>(prob, a.bc, hist, lane, t.n, t.e_true,
                                                         t.flags, t.weight, t.e_reco, nullptr,
                                                         nullptr);
             __syncthreads();

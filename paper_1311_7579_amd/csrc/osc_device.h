@@ -465,31 +465,110 @@ struct EventIn {
     uint32_t f;
 };
 
-// Event i of a tile (0 <= i < kTileEvents) whose arrays start at the
-// tile's first event; n = the tile's events (kTileEvents when FULL).
-// Tile-relative 32-bit indices let every load use the scalar tile base plus
-// a 32-bit lane offset.
-template <int MODE, bool FULL>
-__device__ __forceinline__ EventIn load_event(uint32_t i, uint32_t n, const double* e_true,
+// The arrays of one tile as raw buffer resources (base in SGPRs, size in
+// bytes as the bound): an event's loads and its P store then take the form
+// buffer_load v, lane_offset, rsrc, group_offset -- the lane offset is
+// loop-invariant, the group offset lives in an SGPR, and no per-event
+// address arithmetic runs on the VALU.  Accesses past the bound read 0 and
+// write nothing (the tail guards below still decide what is used).
+constexpr int kBufDword3 = 0x00020000;   // gfx9 family: raw buffer, 32-bit data format
+constexpr int kBufNonTemporal = 2;        // cache-policy operand: the nt bit
+typedef unsigned int BufU2 __attribute__((ext_vector_type(2)));
+
+struct TileBufs {
+    __amdgpu_buffer_rsrc_t e, f, w, x, p;
+};
+
+template <int MODE>
+__device__ __forceinline__ TileBufs tile_bufs(uint32_t n, const double* e_true,
                                               const uint8_t* flags, const double* weight,
-                                              const double* e_reco, const double* value)
+                                              const double* e_reco, const double* value,
+                                              double* p_out)
+{
+    const int nb = int(n * sizeof(double));
+    TileBufs b;
+    b.e = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(MODE == kHist ? value : e_true), 0, nb, kBufDword3);
+    b.f = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(flags), 0, int(n), kBufDword3);
+    b.w = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(weight), 0, nb, kBufDword3);
+    b.x = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(e_reco), 0, nb, kBufDword3);
+    b.p = __builtin_amdgcn_make_buffer_rsrc(p_out, 0, nb, kBufDword3);
+    return b;
+}
+
+__device__ __forceinline__ double buf_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// The same arrays as plain pointers (global loads with 64-bit addresses):
+// the batched kernel keeps this form, where the resources' SGPRs cost more
+// than the address arithmetic they save.
+struct TilePtrs {
+    const double* e;
+    const uint8_t* f;
+    const double* w;
+    const double* x;
+    double* p;
+};
+
+template <int MODE>
+__device__ __forceinline__ TilePtrs tile_ptrs(const double* e_true, const uint8_t* flags,
+                                              const double* weight, const double* e_reco,
+                                              const double* value, double* p_out)
+{
+    return TilePtrs{MODE == kHist ? value : e_true, flags, weight, e_reco, p_out};
+}
+
+template <int MODE, bool FULL>
+__device__ __forceinline__ EventIn load_event(const TilePtrs& b, uint32_t l, uint32_t g0,
+                                              uint32_t n)
 {
     EventIn v;
+    const uint32_t i = l + g0;
     const bool in = FULL || i < n;
-    v.e = in ? (MODE == kHist ? value[i] : e_true[i]) : 1.0;
-    v.f = (MODE != kHist && in) ? uint32_t(flags[i]) : 0u;
-    v.w = (MODE != kReweight && in) ? weight[i] : 0.0;
-    v.x = (MODE != kReweight && in) ? e_reco[i] : 0.0;
+    v.e = in ? b.e[i] : 1.0;
+    v.f = (MODE != kHist && in) ? uint32_t(b.f[i]) : 0u;
+    v.w = (MODE != kReweight && in) ? b.w[i] : 0.0;
+    v.x = (MODE != kReweight && in) ? b.x[i] : 0.0;
     return v;
+}
+
+__device__ __forceinline__ void store_p(const TilePtrs& b, uint32_t l, uint32_t g0, double P)
+{
+    __builtin_nontemporal_store(P, &b.p[l + g0]);
+}
+
+// Event g0 + l of a tile (0 <= g0 + l < kTileEvents); n = the tile's events
+// (kTileEvents when FULL).  g0 is the same for the whole wave.
+template <int MODE, bool FULL>
+__device__ __forceinline__ EventIn load_event(const TileBufs& b, uint32_t l, uint32_t g0,
+                                              uint32_t n)
+{
+    EventIn v;
+    const bool in = FULL || l + g0 < n;
+    const uint32_t l8 = l * 8u, g8 = g0 * 8u;
+    v.e = in ? buf_load_f64(b.e, l8, g8) : 1.0;
+    v.f = (MODE != kHist && in) ? uint32_t(__builtin_amdgcn_raw_buffer_load_b8(b.f, l, g0, 0))
+                                : 0u;
+    v.w = (MODE != kReweight && in) ? buf_load_f64(b.w, l8, g8) : 0.0;
+    v.x = (MODE != kReweight && in) ? buf_load_f64(b.x, l8, g8) : 0.0;
+    return v;
+}
+
+__device__ __forceinline__ void store_p(const TileBufs& b, uint32_t l, uint32_t g0, double P)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(BufU2, P), b.p, l * 8u, g0 * 8u,
+                                          kBufNonTemporal);
 }
 
 // One group of kGroup events of a lane: the probabilities are computed in
 // one straight-line block (no guards: lanes past the end of the sample hold
 // dummy inputs), then stored, binned and accumulated in ascending m.
-template <int MODE, bool WRITE_P, bool FULL, class PROB>
+template <int MODE, bool WRITE_P, bool FULL, class PROB, class ARR>
 __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc, double* hist,
-                                           int lane, uint32_t i0, uint32_t n,
-                                           const EventIn (&ev)[kGroup], double* p_out)
+                                           int lane, uint32_t l, uint32_t g0, uint32_t n,
+                                           const EventIn (&ev)[kGroup], const ARR& arr)
 {
     double P[kGroup], k[kGroup];
     bool edge[kGroup];
@@ -501,10 +580,10 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     if (WRITE_P) {
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
-            const uint32_t i = i0 + j * kTileLanes;
-            // streaming store: P is not read again by this kernel, and
+            const uint32_t gj = g0 + j * kTileLanes;
+            // streaming store (nt): P is not read again by this kernel, and
             // letting it allocate in L2 cost ~10 % of the kernel's time
-            if (FULL || i < n) __builtin_nontemporal_store(P[j], &p_out[i]);
+            if (FULL || l + gj < n) store_p(arr, l, gj, P[j]);
         }
     }
     if (MODE == kReweight) return;
@@ -518,8 +597,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     }
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
-        const uint32_t i = i0 + j * kTileLanes;
-        if (FULL || i < n) {
+        if (FULL || l + g0 + j * kTileLanes < n) {
 #pragma clang fp contract(off)
             const double cval = ev[j].w * P[j];            // rounded, never fused
             const int slot = hslot(lds_bin(k[j], bc), lane & (kHistLanes - 1));
@@ -550,7 +628,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
 // kernel from measurements: rolled for the kernels that write P (both
 // tiers) and for the batched kernel, fully unrolled for the kernels that
 // write no P.
-template <int MODE, bool WRITE_P, bool FULL, bool ROLL, class PROB>
+template <int MODE, bool WRITE_P, bool FULL, bool ROLL, bool BUF = true, class PROB>
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
                                             int lane, uint32_t n, const double* e_true,
                                             const uint8_t* flags, const double* weight,
@@ -559,21 +637,25 @@ __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& b
 {
     constexpr int kGroups = kLaneEvents / kGroup;
     const uint32_t l = uint32_t(lane);
+    const auto bufs = [&] {
+        if constexpr (BUF)
+            return tile_bufs<MODE>(n, e_true, flags, weight, e_reco, value, p_out);
+        else
+            return tile_ptrs<MODE>(e_true, flags, weight, e_reco, value, p_out);
+    }();
     if constexpr (ROLL) {
         EventIn cur[kGroup], nxt[kGroup];
 #pragma unroll
         for (int j = 0; j < kGroup; ++j)
-            cur[j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight, e_reco,
-                                            value);
+            cur[j] = load_event<MODE, FULL>(bufs, l, j * kTileLanes, n);
 #pragma unroll 1
         for (int g = 0; g < kGroups; ++g) {
             const int gn = g + 1 < kGroups ? g + 1 : g;   // the last group reloads itself
 #pragma unroll
             for (int j = 0; j < kGroup; ++j)
-                nxt[j] = load_event<MODE, FULL>(l + (gn * kGroup + j) * kTileLanes, n, e_true,
-                                                flags, weight, e_reco, value);
-            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes, n,
-                                            cur, p_out);
+                nxt[j] = load_event<MODE, FULL>(bufs, l, (gn * kGroup + j) * kTileLanes, n);
+            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l, g * kGroup * kTileLanes, n,
+                                            cur, bufs);
 #pragma unroll
             for (int j = 0; j < kGroup; ++j) cur[j] = nxt[j];
         }
@@ -581,18 +663,17 @@ __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& b
         EventIn ev[kGroups][kGroup];
 #pragma unroll
         for (int j = 0; j < kGroup; ++j)
-            ev[0][j] = load_event<MODE, FULL>(l + j * kTileLanes, n, e_true, flags, weight,
-                                              e_reco, value);
+            ev[0][j] = load_event<MODE, FULL>(bufs, l, j * kTileLanes, n);
 #pragma unroll
         for (int g = 0; g < kGroups; ++g) {
             if (g + 1 < kGroups) {
 #pragma unroll
                 for (int j = 0; j < kGroup; ++j)
-                    ev[g + 1][j] = load_event<MODE, FULL>(l + ((g + 1) * kGroup + j) * kTileLanes,
-                                                          n, e_true, flags, weight, e_reco, value);
+                    ev[g + 1][j] = load_event<MODE, FULL>(bufs, l, ((g + 1) * kGroup + j) * kTileLanes,
+                                                          n);
             }
-            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l + g * kGroup * kTileLanes,
-                                            n, ev[g], p_out);
+            tile_group<MODE, WRITE_P, FULL>(prob, bc, hist, lane, l, g * kGroup * kTileLanes,
+                                            n, ev[g], bufs);
         }
     }
 }
