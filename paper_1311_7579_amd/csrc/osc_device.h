@@ -779,10 +779,10 @@ __device__ __forceinline__ double wave_tree(double v)
 }
 
 // One merge level (see MergeLevel): block (gc, bin, set) reduces chunk gc
-// of the set's input rows for one bin.  Thread t adds its 64 contiguous
-// rows (+0.0 beyond the sample's rows) as a binary tree in registers; the
-// 64 lanes of a wave meet in the butterfly tree and the block's waves in a
-// last tree step.
+// of the set's input rows for one bin.  Thread t adds its kMergeThreadRows
+// contiguous rows (+0.0 beyond the sample's rows) as a binary tree in
+// registers; the 64 lanes of a wave meet in the butterfly tree and the
+// block's waves in a last binary tree.
 template <bool FINAL>
 __device__ __forceinline__ void merge_level_block(const MergeLevel& L, const double* __restrict__ in,
                                                   double* __restrict__ out)
@@ -814,8 +814,15 @@ __device__ __forceinline__ void merge_level_block(const MergeLevel& L, const dou
     if (lane == 0) wave_sum[wave] = r;
     __syncthreads();
     if (t == 0) {
-        static_assert(kMergeWaves == 4, "the block tree below is written for four waves");
-        const double total = (wave_sum[0] + wave_sum[1]) + (wave_sum[2] + wave_sum[3]);
+        // binary tree over the waves' sums, in wave order
+        double w[kMergeWaves];
+#pragma unroll
+        for (int i = 0; i < kMergeWaves; ++i) w[i] = wave_sum[i];
+#pragma unroll
+        for (int h = kMergeWaves / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int i = 0; i < h; ++i) w[i] = w[2 * i] + w[2 * i + 1];
+        const double total = w[0];
         if (FINAL)
             out[(set * L.n_samples + s) * nbt + bin] = total;
         else
