@@ -54,12 +54,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122147.1, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82845.1, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 122169.5, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
+    "write_kib": 82825.0, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
     # quarter-rate transcendentals among them, from the same run
     "valu_per_event": 195.9, "trans_per_event": 8,
-    "source_sha256": "5700539648ef83c0405e79ea8dba8fa9e35fa340116702e3c20ddadd43c63e4a",
+    "source_sha256": "62f73101d553860446d2ddcf66c4a199e9aab1c6e8ffb584b9afc572c46906d8",
 }
 # VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
 # transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.
