@@ -360,13 +360,18 @@ def serving_form(osc, ctx, n_requests):
         warm = workload.make_proposal_stream(64, 500, len(ds))
         serving.run_stream(server, warm, [0.0] * len(warm), ev)
         reqs = workload.make_proposal_stream(n_requests, 501, len(ds))
+        server.reset_stats()
         _, sat = serving.run_stream(server, reqs, [0.0] * n_requests, ev)
         sat_rate = n_requests / sat["wall_s"]
+        st = sat["stats"]
         out["saturation"] = {"requests_per_s": sat_rate, "evals_per_s": sat["evals_per_s"],
-                             "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]}
+                             "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
+                             **{k2: st[k2] for k2 in ("max_in_flight", "max_queued", "budget_waits",
+                                                      "peak_scratch_bytes", "completed")}}
         for k, frac in enumerate((0.5, 0.8, 0.95)):
             reqs = workload.make_proposal_stream(n_requests, 510 + k, len(ds))
             arr = workload.poisson_arrivals(n_requests, frac * sat_rate, 520 + k)
+            server.reset_stats()   # this stream's own counters and maxima
             _, summ = serving.run_stream(server, reqs, arr, ev)
             st = summ.pop("stats")
             summ.update({k2: st[k2] for k2 in ("max_in_flight", "max_queued", "budget_waits",

@@ -292,7 +292,9 @@ typedef struct {
  * (device arrays as in osc_sample; they must stay valid and unchanged for
  * the life of the batch), one binning and one precision, for up to max_sets
  * (1..65535) parameter sets per run.  Allocates the device scratch (tile results of
- * max_sets sets) and chooses a default configuration. */
+ * max_sets sets) and chooses a default configuration.  OSC_ERR_INVALID_ARG
+ * also when max_sets x (the samples' tiles of 1024 events) work items
+ * would overflow the 32-bit work counter of the persistent schedules. */
 osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_samples,
                             const osc_binning* binning, osc_precision precision, int32_t max_sets,
                             osc_batch** out);
@@ -303,7 +305,10 @@ osc_status osc_batch_destroy(osc_batch* batch);
 osc_status osc_batch_get_config(const osc_batch* batch, osc_batch_config* cfg);
 osc_status osc_batch_set_config(osc_batch* batch, const osc_batch_config* cfg);
 
-/* Evaluate n_sets (1..max_sets) parameter sets on every sample: host
+/* Evaluate n_sets (1..max_sets) parameter sets on every sample (with the
+ * one-workgroup-per-tile schedule, OSC_ERR_INVALID_ARG when the work items,
+ * (tiles) x ceil(n_sets / sets_per_item), exceed the 2^32 - 1 work-items of
+ * one grid at 64 per workgroup; the autotuner skips such candidates): host
  * precompute of the sets (Sec. 2.1), an asynchronous upload, one graph
  * replay (kernel + merge) and a device copy of the histograms to hist_out
  * (device, n_sets x n_samples x (nbins + 2) FP64, set-major).  Runs on
@@ -383,6 +388,14 @@ osc_status osc_server_wait(osc_server* server, uint64_t ticket, double* hist, do
                            double* latency_s, double* queue_s);
 
 osc_status osc_server_get_stats(osc_server* server, osc_server_stats* out);
+
+/* Start a new statistics window: the counters (submitted, admitted,
+ * completed, failed, rejected, budget_waits) restart from zero and the
+ * maxima (max_in_flight, max_queued, peak_scratch_bytes) from the current
+ * in-flight count, queue length and scratch in use, so that a later
+ * osc_server_get_stats describes only what happened since.  Requests
+ * already queued or in flight are not affected. */
+osc_status osc_server_reset_stats(osc_server* server);
 
 /* Device scratch (bytes) one request on `sample` takes from the budget. */
 osc_status osc_server_request_bytes(const osc_server* server, int32_t sample, int64_t* bytes);

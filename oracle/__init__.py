@@ -71,6 +71,8 @@ def lib():
                                       vp]
         L.oracle_bin_index_scaled.argtypes = [d, d, d, d, i32]
         L.oracle_bin_index_scaled.restype = i32
+        L.oracle_bin_indices_scaled.argtypes = [i64, vp, d, d, d, i32, vp]
+        L.oracle_bin_indices_scaled.restype = None
         L.oracle_fill_pdf.restype = ctypes.c_int
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_prob_layered.argtypes = [P, i32, vp, vp, vp, d, ctypes.c_int, ctypes.c_int,
@@ -146,10 +148,17 @@ def bin_index(x, lo, hi, nbins) -> int:
 
 
 def bin_indices(x, lo, hi, nbins, e_scale=0.0) -> np.ndarray:
-    L = lib()
-    return np.array([L.oracle_bin_index_scaled(float(v), float(e_scale), float(lo), float(hi),
-                                               int(nbins))
-                     for v in np.asarray(x, dtype=np.float64)], dtype=np.int32)
+    """oracle_bin_index_scaled of every element (one C loop)."""
+    v = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    out = np.empty(v.size, dtype=np.int32)
+    lib().oracle_bin_indices_scaled(v.size, _ptr(v), float(e_scale), float(lo), float(hi),
+                                    int(nbins), _ptr(out))
+    return out
+
+
+def bin_index_scaled(x, lo, hi, nbins, e_scale=0.0) -> int:
+    return lib().oracle_bin_index_scaled(float(x), float(e_scale), float(lo), float(hi),
+                                         int(nbins))
 
 
 def hist_contract(c, bins, nbt, W=CONTRACT_W, K=CONTRACT_K, A=CONTRACT_A) -> np.ndarray:

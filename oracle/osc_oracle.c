@@ -304,6 +304,14 @@ int32_t oracle_bin_index_scaled(double x, double e_scale, double lo, double hi, 
     return oracle_bin_index(xs, lo, hi, nbins);
 }
 
+/* the rule of oracle_bin_index_scaled applied to x[0..n) */
+void oracle_bin_indices_scaled(int64_t n, const double* x, double e_scale, double lo, double hi,
+                               int32_t nbins, int32_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) out[i] = oracle_bin_index_scaled(x[i], e_scale, lo, hi, nbins);
+}
+
 /* complete binary tree sum of v[0..npow2), entries at or beyond nreal
  * counting as +0.0; left subtree + right subtree at every node */
 static double tree_sum(const double* v, int64_t nreal, int64_t npow2)

@@ -92,6 +92,10 @@ int32_t oracle_bin_index(double x, double lo, double hi, int32_t nbins);
  * operations, by the rule above. */
 int32_t oracle_bin_index_scaled(double x, double e_scale, double lo, double hi, int32_t nbins);
 
+/* oracle_bin_index_scaled of every x[i], i < n, into out[i]. */
+void oracle_bin_indices_scaled(int64_t n, const double* x, double e_scale, double lo, double hi,
+                               int32_t nbins, int32_t* out);
+
 /* Deterministic histogram of contributions c[i] into bin[i] (values in
  * [0, nbt)) following the tile reduction contract with tile width W lanes,
  * K events per lane and A accumulators per bin (powers of two, A divides W):

@@ -178,6 +178,20 @@ osc::BatchArgs batch_args(const osc_batch* b, int n_sets, const osc_batch_config
     return a;
 }
 
+// Limits of one launch: a one-workgroup-per-item grid must fit the 32-bit
+// count of work-items (64 per workgroup), and the persistent waves of the
+// dynamic schedule take n_items + grid tickets from a 32-bit counter.
+constexpr int64_t kMaxGridItems = ((int64_t(1) << 32) - 1) / osc::kTileLanes;
+constexpr int64_t kMaxTickets = (int64_t(1) << 32) - 1;
+constexpr int kMaxWavesPerCu = 32;
+
+bool launchable(const osc_batch* b, int n_sets, const osc_batch_config& c)
+{
+    const osc::BatchArgs a = batch_args(b, n_sets, c);
+    if (c.schedule == osc::kOnePerBlock) return a.n_items <= kMaxGridItems;
+    return a.n_items + int64_t(b->num_cus) * kMaxWavesPerCu <= kMaxTickets;
+}
+
 // Enqueues one batched evaluation of n_sets sets (parameters already in
 // d_sets) on `stream`: queue reset, persistent kernel, merge levels.
 hipError_t enqueue(osc_batch* b, int n_sets, const osc_batch_config& c, hipStream_t stream)
@@ -371,6 +385,12 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
     b->num_cus = prop.multiProcessorCount;
     b->occupancy = std::max(1, occ);
     b->cfg = osc_batch_config{8, osc::kDynamic, 0, 1};
+    // the persistent schedules must be able to run every set count up to
+    // max_sets with one set per item
+    if (!launchable(b, max_sets, osc_batch_config{1, osc::kDynamic, 0, 1})) {
+        free_batch(b);
+        return OSC_ERR_INVALID_ARG;
+    }
 
     const size_t scratch = osc::merge_scratch_bytes(b->plan, max_sets);
     const size_t hist_bytes = size_t(max_sets) * n_samples * nbt * sizeof(double);
@@ -428,6 +448,7 @@ osc_status osc_batch_run(osc_batch* b, const osc_params* sets, int32_t n_sets, d
     osc_status st = osc_validate_params(sets, n_sets);
     if (st != OSC_OK) return st;
     std::lock_guard<std::mutex> lock(b->mu);
+    if (!launchable(b, n_sets, b->cfg)) return OSC_ERR_INVALID_ARG;
     if (hipSetDevice(b->device) != hipSuccess) return OSC_ERR_DEVICE;
     const hipStream_t hs = static_cast<hipStream_t>(stream);
     st = stage_sets(b, sets, n_sets, hs);
@@ -462,8 +483,10 @@ osc_status osc_batch_tune(osc_batch* b, const osc_params* sets, int32_t n_sets,
     std::vector<osc_batch_config> cands;
     for (int spi : {1, 2, 4, 8, 16})
         if (spi <= n_sets || spi == 1)
-            for (int sched : {int(osc::kDynamic), int(osc::kStatic), int(osc::kOnePerBlock)})
-                cands.push_back(osc_batch_config{spi, sched, 0, 1});
+            for (int sched : {int(osc::kDynamic), int(osc::kStatic), int(osc::kOnePerBlock)}) {
+                const osc_batch_config c{spi, sched, 0, 1};
+                if (launchable(b, n_sets, c)) cands.push_back(c);
+            }
     hipEvent_t t0 = nullptr, t1 = nullptr;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return OSC_ERR_DEVICE;
     double best = 1e300;

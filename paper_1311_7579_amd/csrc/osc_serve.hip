@@ -427,6 +427,19 @@ osc_status osc_server_get_stats(osc_server* sv, osc_server_stats* out)
     return OSC_OK;
 }
 
+osc_status osc_server_reset_stats(osc_server* sv)
+{
+    if (!sv) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(sv->mu);
+    const int64_t in_flight = sv->stats.in_flight;
+    sv->stats = osc_server_stats{};
+    sv->stats.in_flight = in_flight;
+    sv->stats.max_in_flight = in_flight;
+    sv->stats.max_queued = int64_t(sv->pending.size());
+    sv->stats.peak_scratch_bytes = int64_t(sv->arena.used());
+    return OSC_OK;
+}
+
 osc_status osc_server_request_bytes(const osc_server* sv, int32_t sample, int64_t* bytes)
 {
     if (!sv || !bytes || sample < 0 || size_t(sample) >= sv->samples.size())

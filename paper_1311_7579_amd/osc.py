@@ -180,6 +180,8 @@ def load():
     L.osc_server_set_data.restype = st
     L.osc_server_get_stats.argtypes = [vp, ctypes.POINTER(osc_server_stats)]
     L.osc_server_get_stats.restype = st
+    L.osc_server_reset_stats.argtypes = [vp]
+    L.osc_server_reset_stats.restype = st
     L.osc_server_request_bytes.argtypes = [vp, i32, ctypes.POINTER(i64)]
     L.osc_server_request_bytes.restype = st
     L.osc_status_string.argtypes = [ctypes.c_int]
@@ -220,6 +222,54 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _vec_layout(t, name, dtype, n=None, multiple_of=None, optional=False):
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, not {type(t).__name__}")
+    if t.dtype != getattr(torch, dtype):
+        raise ValueError(f"{name} must be {dtype}, not {str(t.dtype).replace('torch.', '')}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries, not {t.numel()}")
+    if multiple_of is not None and t.numel() % multiple_of:
+        raise ValueError(f"{name} must have a multiple of {multiple_of} entries, not {t.numel()}")
+
+
+def _vec_device(t, name, device):
+    if t is None:
+        return None
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be in GPU memory, not on {t.device}")
+    if device is not None and t.device.index not in (None, device):
+        raise ValueError(f"{name} is on GPU {t.device.index}, the context on GPU {device}")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
+
+
+def device_vecs(*specs, device=None):
+    """Check the tensors a kernel will read or write through their data
+    pointers.  Each spec is (tensor, name, dtype, {n, multiple_of,
+    optional}): a contiguous torch tensor of `dtype` (``"float64"`` or
+    ``"uint8"``) with exactly `n` entries (or a multiple of `multiple_of`);
+    None only when optional.  Then every tensor must be in GPU memory, on
+    device index `device` when given.  Raises ValueError before anything
+    reaches the library; returns the data pointers (None for absent or
+    empty tensors)."""
+    for t, name, dtype, *kw in specs:
+        _vec_layout(t, name, dtype, **(kw[0] if kw else {}))
+    ptrs = [_vec_device(t, name, device) for t, name, *_ in specs]
+    return ptrs if len(ptrs) != 1 else ptrs[0]
+
+
+def device_vec(t, name, dtype, device=None, **kw):
+    """device_vecs for one tensor."""
+    return device_vecs((t, name, dtype, kw), device=device)
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -250,13 +300,29 @@ class DeviceSample:
     rho_gcc: float = 2.6
     Ye: float = 0.5
 
+    def __post_init__(self):
+        _vec_layout(self.e_true, "e_true", "float64")
+        n = self.n
+        device_vecs((self.e_true, "e_true", "float64"), (self.flags, "flags", "uint8", dict(n=n)),
+                    (self.weight, "weight", "float64", dict(n=n, optional=True)),
+                    (self.e_reco, "e_reco", "float64", dict(n=n, optional=True)),
+                    device=self.e_true.device.index)
+
     @property
     def n(self) -> int:
         return int(self.e_true.numel())
 
+    @property
+    def device(self):
+        return self.e_true.device.index
+
     def c_struct(self) -> osc_sample:
         return osc_sample(self.n, _ptr(self.e_true), _ptr(self.flags), _ptr(self.weight),
                           _ptr(self.e_reco), float(self.L_km), float(self.rho_gcc), float(self.Ye))
+
+    def require_hist_inputs(self):
+        if self.weight is None or self.e_reco is None:
+            raise ValueError("this call reads weight and e_reco; the sample has none")
 
     @classmethod
     def from_host(cls, s, device="cuda"):
@@ -307,23 +373,43 @@ class Context:
         arr = params_array(sets)
         _check(load().osc_set_params(self.handle, arr, len(arr)), "osc_set_params")
 
+    def _sample(self, sample, hist_inputs):
+        if not isinstance(sample, DeviceSample):
+            raise ValueError("sample must be a DeviceSample")
+        if sample.device not in (None, self.device):
+            raise ValueError(f"the sample is on GPU {sample.device}, the context on "
+                             f"GPU {self.device}")
+        if hist_inputs:
+            sample.require_hist_inputs()
+        return sample.c_struct()
+
+    @staticmethod
+    def _hist(hist_out, nbins):
+        if int(nbins) < 1:
+            raise ValueError("nbins must be at least 1")
+        return (hist_out, "hist_out", "float64", dict(n=int(nbins) + 2))
+
     def osc_reweight(self, sample: DeviceSample, set_index, p_out, stream=None):
-        cs = sample.c_struct()
-        _check(load().osc_reweight(self.handle, ctypes.byref(cs), int(set_index), _ptr(p_out),
+        cs = self._sample(sample, False)
+        pp = device_vec(p_out, "p_out", "float64", n=sample.n, device=self.device)
+        _check(load().osc_reweight(self.handle, ctypes.byref(cs), int(set_index), pp,
                                    _stream(stream)), "osc_reweight")
 
     def osc_fill_pdf(self, sample: DeviceSample, set_index, nbins, lo, hi, hist_out,
                      p_out=None, precision=OSC_FP64, stream=None, e_scale=0.0):
-        cs = sample.c_struct()
+        cs = self._sample(sample, True)
+        hp, pp = device_vecs(self._hist(hist_out, nbins),
+                             (p_out, "p_out", "float64", dict(n=sample.n, optional=True)),
+                             device=self.device)
         b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
         _check(load().osc_fill_pdf(self.handle, ctypes.byref(cs), int(set_index), ctypes.byref(b),
-                                   int(precision), _ptr(hist_out), _ptr(p_out), _stream(stream)),
+                                   int(precision), hp, pp, _stream(stream)),
                "osc_fill_pdf")
 
     def osc_validate_sample(self, sample: DeviceSample, stream=None):
         """(events with a true energy that is not finite and > 0, events with
         an invalid flag byte)."""
-        cs = sample.c_struct()
+        cs = self._sample(sample, False)
         be, bf = ctypes.c_int64(), ctypes.c_int64()
         _check(load().osc_validate_sample(self.handle, ctypes.byref(cs), ctypes.byref(be),
                                           ctypes.byref(bf), _stream(stream)),
@@ -331,20 +417,24 @@ class Context:
         return be.value, bf.value
 
     def osc_reweight_layered(self, sample: DeviceSample, layers, set_index, p_out, stream=None):
-        cs = sample.c_struct()
+        cs = self._sample(sample, False)
+        pp = device_vec(p_out, "p_out", "float64", n=sample.n, device=self.device)
         arr = layers_array(layers)
         _check(load().osc_reweight_layered(self.handle, ctypes.byref(cs), arr, len(arr),
-                                           int(set_index), _ptr(p_out), _stream(stream)),
+                                           int(set_index), pp, _stream(stream)),
                "osc_reweight_layered")
 
     def osc_fill_pdf_layered(self, sample: DeviceSample, layers, set_index, nbins, lo, hi,
                              hist_out, p_out=None, stream=None, e_scale=0.0):
-        cs = sample.c_struct()
+        cs = self._sample(sample, True)
+        hp, pp = device_vecs(self._hist(hist_out, nbins),
+                             (p_out, "p_out", "float64", dict(n=sample.n, optional=True)),
+                             device=self.device)
         arr = layers_array(layers)
         b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
         _check(load().osc_fill_pdf_layered(self.handle, ctypes.byref(cs), arr, len(arr),
-                                           int(set_index), ctypes.byref(b), _ptr(hist_out),
-                                           _ptr(p_out), _stream(stream)), "osc_fill_pdf_layered")
+                                           int(set_index), ctypes.byref(b), hp, pp,
+                                           _stream(stream)), "osc_fill_pdf_layered")
 
     def osc_profile_enable(self, on=True):
         _check(load().osc_profile_enable(self.handle, int(bool(on))), "osc_profile_enable")
@@ -363,19 +453,32 @@ class Context:
         mu_scale, against the rows of `data` (n_data, nbins); histogram k
         uses row k % n_data."""
         nbins = int(data.shape[-1])
+        if nbins < 1:
+            raise ValueError("data must have at least one bin")
+        _vec_layout(hist, "hist", "float64", multiple_of=nbins + 2)
+        _vec_layout(data, "data", "float64", multiple_of=nbins)
         n_hist = int(hist.numel() // (nbins + 2))
         n_data = int(data.numel() // nbins)
-        _check(load().osc_poisson_nll(self.handle, _ptr(hist), n_hist, float(mu_scale), _ptr(data),
-                                      n_data, nbins, _ptr(nll_out), _stream(stream)),
+        if n_data < 1:
+            raise ValueError("data must hold at least one row")
+        hp, dp, op = device_vecs((hist, "hist", "float64"), (data, "data", "float64"),
+                                 (nll_out, "nll_out", "float64", dict(n=n_hist)),
+                                 device=self.device)
+        _check(load().osc_poisson_nll(self.handle, hp, n_hist, float(mu_scale), dp,
+                                      n_data, nbins, op, _stream(stream)),
                "osc_poisson_nll")
 
     def osc_fill_hist(self, value, weight, e_reco, nbins, lo, hi, hist_out, stream=None,
                       e_scale=0.0):
         b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
+        _vec_layout(value, "value", "float64")
         n = int(value.numel())
-        _check(load().osc_fill_hist(self.handle, n, _ptr(value), _ptr(weight), _ptr(e_reco),
-                                    ctypes.byref(b), _ptr(hist_out), _stream(stream)),
-               "osc_fill_hist")
+        vp, wp, xp, hp = device_vecs((value, "value", "float64"),
+                                     (weight, "weight", "float64", dict(n=n)),
+                                     (e_reco, "e_reco", "float64", dict(n=n)),
+                                     self._hist(hist_out, nbins), device=self.device)
+        _check(load().osc_fill_hist(self.handle, n, vp, wp, xp, ctypes.byref(b), hp,
+                                    _stream(stream)), "osc_fill_hist")
 
 
 N_CHANNELS = 18   # alpha + 3 beta + 9 anti
@@ -389,7 +492,7 @@ class Template:
                  e_scale=0.0):
         self.ctx = ctx
         self.nt, self.nr = int(nt), int(nr)
-        cs = sample.c_struct()
+        cs = ctx._sample(sample, True)
         tb = osc_binning(self.nt, float(lo_t), float(hi_t), 0.0)
         rb = osc_binning(self.nr, float(lo_r), float(hi_r), float(e_scale))
         h = ctypes.c_void_p()
@@ -420,8 +523,11 @@ class Template:
         return out
 
     def fill_pdf(self, set_index, hist_out, p_centre_out=None, stream=None):
-        _check(load().osc_fill_pdf_bincentre(self.ctx.handle, self.handle, int(set_index),
-                                             _ptr(hist_out), _ptr(p_centre_out),
+        hp, cp = device_vecs(self.ctx._hist(hist_out, self.nr),
+                             (p_centre_out, "p_centre_out", "float64",
+                              dict(n=N_CHANNELS * self.nt, optional=True)),
+                             device=self.ctx.device)
+        _check(load().osc_fill_pdf_bincentre(self.ctx.handle, self.handle, int(set_index), hp, cp,
                                              _stream(stream)), "osc_fill_pdf_bincentre")
 
 
@@ -437,7 +543,7 @@ class Batch:
         self.samples = list(samples)
         self.nbins = int(nbins)
         self.max_sets = int(max_sets)
-        arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
+        arr = (osc_sample * len(self.samples))(*[ctx._sample(s, True) for s in self.samples])
         b = osc_binning(self.nbins, float(lo), float(hi), float(e_scale))
         h = ctypes.c_void_p()
         _check(load().osc_batch_create(ctx.handle, arr, len(self.samples), ctypes.byref(b),
@@ -478,7 +584,9 @@ class Batch:
         if hist_out is None:
             hist_out = torch.empty((len(arr), len(self.samples), self.nbins + 2),
                                    dtype=torch.float64, device=self.samples[0].e_true.device)
-        _check(load().osc_batch_run(self.handle, arr, len(arr), _ptr(hist_out), _stream(stream)),
+        hp = device_vec(hist_out, "hist_out", "float64",
+                        n=len(arr) * len(self.samples) * (self.nbins + 2), device=self.ctx.device)
+        _check(load().osc_batch_run(self.handle, arr, len(arr), hp, _stream(stream)),
                "osc_batch_run")
         return hist_out
 
@@ -508,7 +616,7 @@ class Server:
         self.ctx = ctx
         self.samples = list(samples)
         self.nbins = int(nbins)
-        arr = (osc_sample * len(self.samples))(*[s.c_struct() for s in self.samples])
+        arr = (osc_sample * len(self.samples))(*[ctx._sample(s, True) for s in self.samples])
         b = osc_binning(self.nbins, float(lo), float(hi), float(e_scale))
         cfg = osc_server_config(int(slots), int(queue_capacity), int(scratch_budget_bytes))
         h = ctypes.c_void_p()
@@ -574,6 +682,11 @@ class Server:
         s = osc_server_stats()
         _check(load().osc_server_get_stats(self.handle, ctypes.byref(s)), "osc_server_get_stats")
         return s.as_dict()
+
+    def reset_stats(self):
+        """Start a new statistics window (counters from zero, maxima from
+        the current state)."""
+        _check(load().osc_server_reset_stats(self.handle), "osc_server_reset_stats")
 
     def request_bytes(self, sample) -> int:
         b = ctypes.c_int64()

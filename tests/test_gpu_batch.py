@@ -9,6 +9,7 @@ import pytest
 
 import oracle
 from paper_1311_7579_amd import workload
+from helpers import MIXED_TOL, P_TOL, assert_bits_equal, hist_tolerance
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -83,23 +84,53 @@ def test_batch_graph_replays_with_changing_sets(osc, ctx, small):
         batch.close()
 
 
-def test_batch_against_oracle(osc, ctx):
-    samples = workload.make_batched_samples(sizes=(20_000, 30_000), L_km=(295.0, 2500.0),
+def batch_vs_oracle(osc, ctx, samples, ds, sets, got, precision, pick, what):
+    """Every picked (set, sample) histogram of a batched run against the
+    oracle: bit-exact against the contract replayed on c = w * P with P from
+    a plain call of the same set, sample and tier, and within the tier's P
+    tolerance (carried through the weights) of the oracle's own PDF.
+    Returns the largest |dh| / tolerance."""
+    p_tol = P_TOL if precision == osc.OSC_FP64 else MIXED_TOL
+    worst = 0.0
+    for j, s in enumerate(samples):
+        bins = oracle.bin_indices(s.e_reco, 0.0, 3.0, 50)
+        p_gpu = torch.empty(s.n, dtype=torch.float64, device="cuda")
+        h = torch.empty(52, dtype=torch.float64, device="cuda")
+        for k in pick:
+            ctx.osc_set_params([sets[k]])
+            ctx.osc_fill_pdf(ds[j], 0, 50, 0.0, 3.0, h, p_gpu, precision=precision)
+            P = p_gpu.cpu().numpy()
+            assert_bits_equal(got[k, j], oracle.hist_contract(s.weight * P, bins, 52),
+                              f"{what} set {k} sample {j}")
+            h_o, P_o = oracle.fill_pdf(sets[k], s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                       s.weight, s.e_reco, 50, 0.0, 3.0)
+            sub = slice(0, min(s.n, 200_000))
+            assert np.abs(P[sub] - P_o[sub]).max() <= p_tol, (what, k, j)
+            tol = hist_tolerance(s.weight, s.weight * P_o, bins, 52, s.n, p_tol=p_tol)
+            dev = np.abs(got[k, j] - h_o)
+            assert (dev <= tol).all(), (what, k, j)
+            worst = max(worst, float(np.max(np.divide(dev, tol, out=np.zeros_like(dev),
+                                                      where=tol > 0))))
+    return worst
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("spi,sched", [(1, 0), (3, 0), (4, 2)])
+def test_batch_against_oracle(osc, ctx, precision, spi, sched):
+    """Both tiers, several sets per item and two schedules, two samples of
+    uneven size at 295 and 2500 km: every histogram against the oracle."""
+    samples = workload.make_batched_samples(sizes=(20_000, 30_001), L_km=(295.0, 2500.0),
                                             seeds=(5, 6))
     ds = [osc.DeviceSample.from_host(s) for s in samples]
-    sets = workload.make_param_sets(3, 21)
-    batch = osc.Batch(ctx, ds, 50, 0.0, 3.0, precision=0, max_sets=4)
+    sets = workload.make_param_sets(5, 21)
+    batch = osc.Batch(ctx, ds, 50, 0.0, 3.0, precision=precision, max_sets=8)
     try:
+        batch.config = dict(sets_per_item=spi, schedule=sched, use_graph=1)
         got = batch.run(sets).cpu().numpy()
     finally:
         batch.close()
-    for k, p in enumerate(sets):
-        for j, s in enumerate(samples):
-            h, P = oracle.fill_pdf(p, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags, s.weight,
-                                   s.e_reco, 50, 0.0, 3.0)
-            sw = np.bincount(oracle.bin_indices(s.e_reco, 0.0, 3.0, 50), weights=s.weight,
-                             minlength=52)
-            assert (np.abs(got[k, j] - h) <= 1e-12 * sw + 1e-12).all()
+    batch_vs_oracle(osc, ctx, samples, ds, sets, got, precision, range(len(sets)),
+                    f"tier {precision} spi {spi} schedule {sched}")
 
 
 def test_batch_tune_and_cache(osc, ctx, small, tmp_path):
@@ -135,17 +166,35 @@ def test_batch_invalid_arguments(osc, ctx, small):
             batch.config = dict(sets_per_item=0)
     finally:
         batch.close()
+    # 16 samples of 2^32 events x 65535 sets one per item would overflow the
+    # 32-bit work counter: refused before any allocation (the arrays are
+    # never read, so one small tensor stands for all of them)
+    import ctypes
+    e = ds[0]
+    big = (osc.osc_sample * 16)(*[osc.osc_sample(1 << 32, e.e_true.data_ptr(), e.flags.data_ptr(),
+                                                 e.weight.data_ptr(), e.e_reco.data_ptr(), 295.0,
+                                                 2.6, 0.5) for _ in range(16)])
+    b = osc.osc_binning(50, 0.0, 3.0, 0.0)
+    h = ctypes.c_void_p()
+    st = osc.load().osc_batch_create(ctx.handle, big, 16, ctypes.byref(b), 1, 65535,
+                                     ctypes.byref(h))
+    assert st == osc.OSC_ERR_INVALID_ARG and not h.value
 
 
-def test_batch_full_workload(osc, ctx):
+@pytest.mark.parametrize("precision", [1, 0])
+def test_batch_full_workload(osc, ctx, precision):
     """256 parameter sets x 4 samples of 1e5, 5e5, 2e6, 5e6 events (295,
-    810, 1300, 2500 km), mixed tier: sampled (set, sample) pairs equal the
-    plain call bit for bit."""
+    810, 1300, 2500 km), both tiers, the tuned configuration: sampled
+    (set, sample) pairs equal the plain call bit for bit and match the
+    oracle (bit-exact against the contract on the plain call's P, within
+    the tier's tolerance of the oracle's PDF over all events; per-event P
+    against the oracle on a 2e5-event sub-sample)."""
     samples = workload.make_batched_samples()
     ds = [osc.DeviceSample.from_host(s) for s in samples]
     sets = workload.make_param_sets(256, 4)
-    batch = osc.Batch(ctx, ds, 50, 0.0, 3.0, precision=1, max_sets=256)
+    batch = osc.Batch(ctx, ds, 50, 0.0, 3.0, precision=precision, max_sets=256)
     try:
+        batch.config = dict(sets_per_item=8, schedule=osc.SCHEDULE_ONE_PER_BLOCK, use_graph=1)
         got = batch.run(sets).cpu().numpy()
     finally:
         batch.close()
@@ -154,6 +203,9 @@ def test_batch_full_workload(osc, ctx):
     h = torch.empty(52, dtype=torch.float64, device="cuda")
     for i, k in enumerate(pick):
         for j in range(4):
-            ctx.osc_fill_pdf(ds[j], i, 50, 0.0, 3.0, h, None, precision=1)
+            ctx.osc_fill_pdf(ds[j], i, 50, 0.0, 3.0, h, None, precision=precision)
             np.testing.assert_array_equal(h.cpu().numpy(), got[k, j], err_msg=f"set {k} sample {j}")
     assert np.isfinite(got).all()
+    worst = batch_vs_oracle(osc, ctx, samples, ds, sets, got, precision, [0, 131, 255],
+                            f"full workload tier {precision}")
+    print(f"batched full workload, tier {precision}: largest |dh| / tolerance {worst:.3g}")

@@ -14,20 +14,16 @@ Tolerances:
   * osc_fill_pdf's histogram is bit-identical to osc_fill_hist applied to
     its own per-event P (the reduction is the same), run to run.
 """
-import math
-
 import numpy as np
 import pytest
 
 import oracle
 from paper_1311_7579_amd import workload
-from helpers import bins_np
+from helpers import P_TOL, MIXED_TOL, assert_bits_equal, bins_np, hist_tolerance
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-
-P_TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -69,15 +65,6 @@ def gpu_fill_pdf(osc, ctx, s, nbins, lo, hi, set_index=0, want_p=True):
     p = torch.empty(s.n, dtype=torch.float64, device="cuda") if want_p else None
     ctx.osc_fill_pdf(ds, set_index, nbins, lo, hi, h, p)
     return host(h), (host(p) if want_p else None)
-
-
-def hist_tolerance(w, c, bins, nbt, n):
-    W, K, A = oracle.CONTRACT_W, oracle.CONTRACT_K, oracle.CONTRACT_A
-    ntiles = max(1, -(-n // (W * K)))
-    depth = K * W // A + int(math.log2(A)) + math.ceil(math.log2(ntiles)) + 1
-    sw = np.bincount(bins, weights=np.abs(w), minlength=nbt)
-    sc = np.bincount(bins, weights=np.abs(c), minlength=nbt)
-    return P_TOL * sw + 2 * depth * 2.0 ** -53 * sc
 
 
 # --------------------------------------------------------------- per event
@@ -353,6 +340,101 @@ def test_fill_hist_bin_edges_exact(osc, ctx, nbins, lo, hi):
     np.testing.assert_array_equal(host(h), oracle.hist_contract(w, bins, nbins + 2))
 
 
+def edge_contributions(seed):
+    """Events (value, weight, reco energy) whose contributions c = w * v sit
+    at the numeric edges of FP64, grouped by bin of 10 on [0, 10):
+    bin 0 subnormal sums (products that round into the subnormal range,
+    sums that cross 2^-1022 both ways), bin 1 signed normals cancelling to
+    exact zero and to subnormals, bin 2 only -0.0 and +0.0 (the result
+    must be +0.0), bin 3 magnitudes 2^500 and 2^-500 of both signs, bin 4
+    sums that overflow to +inf, bin 5 +inf among finite values, bin 6 +inf
+    and -inf (NaN), bin 7 NaN among finite values, bin 8 all of the above
+    in one bin (NaN), bin 10 the finite ones of them in one bin; bin 9
+    ordinary values.  The events are shuffled so the bins
+    interleave across lanes, accumulators and tiles."""
+    rng = np.random.default_rng(seed)
+    tiny, dmin = 2.0 ** -1074, 2.0 ** -1022
+    groups = {
+        0: [k * tiny for k in rng.integers(-2 ** 20, 2 ** 20, 400)] + [dmin - tiny, tiny, -tiny,
+                                                                     dmin, -dmin, 3 * tiny],
+        1: [1e-300, -1e-300, 3.5, -3.5, dmin, -(dmin - 5 * tiny), -1.25, 1.25, 7e-310,
+            -7e-310] + list(rng.uniform(-1, 1, 200)),
+        2: [-0.0] * 50 + [0.0] * 3 + [-0.0] * 50,
+        3: [2.0 ** 500, -(2.0 ** 500), 2.0 ** -500, -(2.0 ** -500), 3 * 2.0 ** 500, 1.0,
+            -(2.0 ** -499)] * 20,
+        4: [1.5 * 2.0 ** 1023, 1.5 * 2.0 ** 1023, -1.0, 2.0],
+        5: [1.0, np.inf, -3.0, 2.0 ** 500],
+        6: [np.inf, 1.0, -np.inf],
+        7: [1.0, np.nan, -2.0],
+        9: list(rng.uniform(0.5, 1.5, 300)),
+    }
+    finite = [g[k] for b, g in groups.items() if b in (0, 1, 2, 3, 9) for k in range(0, len(g), 5)]
+    groups[8] = finite + [np.inf, -np.inf, np.nan, -0.0]
+    groups[10] = finite
+    c = np.concatenate([np.asarray(v, dtype=np.float64) for v in groups.values()])
+    x = np.concatenate([np.full(len(v), b + 0.5) for b, v in groups.items()])
+    # value x weight = c exactly: ordinary contributions as (c, 1), and every
+    # third one split into a product that the multiply itself must round
+    # into place (2^-600 x 2^-474 = 2^-1074, 2^-520 x (c 2^520))
+    v = np.ones_like(c)
+    w = c.copy()
+    sel = (np.arange(c.size) % 3 == 0) & np.isfinite(c) & (np.abs(c) < 2.0 ** 400) & (c != 0)
+    v[sel] = 2.0 ** -520
+    w[sel] = c[sel] * 2.0 ** 520
+    v[0], w[0] = 2.0 ** -600, 2.0 ** -474
+    perm = rng.permutation(c.size)
+    return v[perm], w[perm], x[perm]
+
+
+@pytest.mark.parametrize("copies", [1, 3])
+def test_fill_hist_numeric_edges_bit_exact(osc, ctx, copies):
+    """The reduction at the numeric edges: subnormal, negative, +-0.0,
+    +-inf, NaN and 2^+-500 contributions, alone and all in one bin, over
+    one and several tiles, bit for bit against the oracle's contract replay
+    (NaN only as NaN)."""
+    parts = [edge_contributions(90 + k) for k in range(copies)]
+    v, w, x = (np.concatenate([p[i] for p in parts]) for i in range(3))
+    h = torch.empty(13, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_hist(dev(v), dev(w), dev(x), 11, 0.0, 11.0, h)
+    bins = oracle.bin_indices(x, 0.0, 11.0, 11)
+    want = oracle.hist_contract(w * v, bins, 13)
+    got = host(h)
+    assert_bits_equal(got, want, f"{copies} copies")
+    # the expected classes of results, so that the edges really were hit
+    assert np.isnan(got[[6, 7, 8]]).all() and got[4] == np.inf and got[5] == np.inf
+    assert got[2] == 0.0 and not np.signbit(got[2])
+    assert np.isfinite(got[[0, 1, 3, 9, 10]]).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fill_pdf_invalid_flags_nan_bins(osc, ctx, precision):
+    """Events with invalid flag bytes have P = NaN, so the bins they fall
+    into are NaN in both tiers; every bin is bit-exact against the contract
+    applied to the kernel's own P, NaN in the same bins as the oracle's
+    histogram, and within the tier's tolerance of it elsewhere."""
+    prec = osc.OSC_FP64 if precision == "fp64" else osc.OSC_FP32_MIXED
+    tol_p = P_TOL if precision == "fp64" else MIXED_TOL
+    s = workload.make_sample(70_001, 13)
+    bad = np.array([5, 1030, 1031, 40_000, 70_000])
+    s.flags[bad] = np.array([3, 0xFF, 1 << 5, 3 << 2, 35], dtype=np.uint8)
+    s.e_reco[bad] = np.array([0.01, 1.21, 1.23, 2.99, 7.0])    # bins 0, 20, 20, 49, overflow
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, p, precision=prec)
+    got, P = host(h), host(p)
+    assert np.isnan(P[bad]).all() and np.isfinite(np.delete(P, bad)).all()
+    bins = oracle.bin_indices(s.e_reco, 0.0, 3.0, 50)
+    assert_bits_equal(got, oracle.hist_contract(s.weight * P, bins, 52), precision)
+    hist_o, P_o = oracle.fill_pdf(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                  s.weight, s.e_reco, 50, 0.0, 3.0)
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(hist_o))
+    assert np.isnan(got[[0, 20, 49, 51]]).all()
+    fin = ~np.isnan(hist_o)
+    tol = hist_tolerance(s.weight, s.weight * np.nan_to_num(P_o), bins, 52, s.n, p_tol=tol_p)
+    assert (np.abs(got - hist_o)[fin] <= tol[fin]).all()
+
+
 def test_fill_hist_max_nbins(osc, ctx):
     nb = ctx.max_nbins
     assert nb >= 200
@@ -471,12 +553,7 @@ def test_invalid_arguments_raise(osc, ctx):
 
 # --------------------------------------------------------------- FP32-mixed tier
 # FP64 eigenvalues and phase differences, FP32 sine/cosine and amplitude
-# assembly.  The tolerance comes from the FP32 rounding of the amplitude
-# inputs: N_k carries ~|u m| 2^-24 ~ 4e-13 eV^4 of rounding, divided by
-# D_k >= ~1.7e-7 eV^4 near the solar resonance, i.e. ~2e-6 per projector
-# element; the hardware sine/cosine add ~1e-6.  The bound below doubles the
-# sum over the three projector terms.
-MIXED_TOL = 2e-5
+# assembly; the tier's tolerance MIXED_TOL is derived in helpers.py.
 
 
 def test_mixed_tier_c3_parameter_sets(osc, ctx):

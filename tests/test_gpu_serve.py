@@ -1,10 +1,15 @@
-"""GPU tests of the serving form (osc_server_*): results are bit-identical
-to osc_fill_pdf alone and in a concurrent mix, admission respects the slot
-count and the scratch budget, the queue refuses what it cannot take."""
+"""GPU tests of the serving form (osc_server_*): every served histogram
+against the CPU oracle (bit for bit against the contract applied to the
+request's own per-event P, and within the tier's tolerance of the oracle's
+PDF), results bit-identical to osc_fill_pdf alone and in a concurrent mix,
+admission by slot count and scratch budget, the queue refusing what it
+cannot take."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_1311_7579_amd import workload
+from helpers import MIXED_TOL, P_TOL, assert_bits_equal, hist_tolerance
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,12 +38,50 @@ def resident(osc):
     return samples, [osc.DeviceSample.from_host(s) for s in samples]
 
 
-def plain(osc, ctx, ds, params, tier):
+def plain(osc, ctx, ds, params, tier, want_p=False):
     ctx.osc_set_params([params])
     h = torch.empty(52, dtype=torch.float64, device="cuda")
-    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, None, precision=tier)
+    p = torch.empty(ds.n, dtype=torch.float64, device="cuda") if want_p else None
+    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, p, precision=tier)
     torch.cuda.synchronize()
-    return h.cpu().numpy()
+    return (h.cpu().numpy(), p.cpu().numpy()) if want_p else h.cpu().numpy()
+
+
+class OracleCheck:
+    """Compares a served histogram of (params, sample, tier) with the CPU
+    oracle: bit-exact against the oracle's replay of the reduction contract
+    on c = w * P, with P the per-event probabilities of a plain call of the
+    same set, sample and tier; within the tier's P tolerance, carried
+    through the weights, of the oracle's own PDF (its own P)."""
+
+    def __init__(self, osc, ctx, samples, ds):
+        self.osc, self.ctx, self.samples, self.ds = osc, ctx, samples, ds
+        self.bins = [oracle.bin_indices(s.e_reco, 0.0, 3.0, 50) for s in samples]
+        self.checked = {0: 0, 1: 0}
+        self.worst = {0: 0.0, 1: 0.0}
+        self.cache = {}
+
+    def expected(self, params, sample, tier):
+        key = (tuple(params[f] for f in workload.PARAM_FIELDS), sample, tier)
+        if key not in self.cache:
+            s, b = self.samples[sample], self.bins[sample]
+            _, P = plain(self.osc, self.ctx, self.ds[sample], params, tier, want_p=True)
+            h_o, P_o = oracle.fill_pdf(params, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                       s.weight, s.e_reco, 50, 0.0, 3.0)
+            p_tol = P_TOL if tier == self.osc.OSC_FP64 else MIXED_TOL
+            assert np.abs(P - P_o).max() <= p_tol, key
+            self.cache[key] = (oracle.hist_contract(s.weight * P, b, 52), h_o,
+                               hist_tolerance(s.weight, s.weight * P_o, b, 52, s.n, p_tol=p_tol))
+        return self.cache[key]
+
+    def __call__(self, hist, params, sample, tier, what):
+        replay, h_o, tol = self.expected(params, sample, tier)
+        assert_bits_equal(hist, replay, what)
+        dev = np.abs(hist - h_o)
+        ratio = float(np.max(np.divide(dev, tol, out=np.zeros_like(dev), where=tol > 0)))
+        assert (dev <= tol).all(), (what, ratio)
+        self.checked[tier] += 1
+        self.worst[tier] = max(self.worst[tier], ratio)
 
 
 def test_server_alone_equals_mix_equals_plain(osc, ctx, resident):
@@ -54,10 +97,16 @@ def test_server_alone_equals_mix_equals_plain(osc, ctx, resident):
         st = server.stats()
     finally:
         server.close()
+    check = OracleCheck(osc, ctx, samples, ds)
     for k, (p, s, tier) in enumerate(reqs):
+        check(alone[k], p, s, tier, f"request {k} alone")
+        check(mix[k], p, s, tier, f"request {k} in the mix")
         np.testing.assert_array_equal(alone[k], mix[k], err_msg=f"request {k}")
         np.testing.assert_array_equal(alone[k], plain(osc, ctx, ds[s], p, tier),
                                       err_msg=f"request {k} vs plain")
+    assert check.checked[0] >= 10 and check.checked[1] >= 10     # both tiers served
+    print(f"served vs oracle: {check.checked} histograms, largest |dh| / tolerance "
+          f"FP64 {check.worst[0]:.3g}, FP32-mixed {check.worst[1]:.3g}")
     assert st["completed"] == 80 and st["failed"] == 0
     assert st["max_in_flight"] > 1          # the mix really ran concurrently
 
@@ -82,6 +131,10 @@ def test_server_admission_by_budget(osc, ctx, resident):
     assert st["peak_scratch_bytes"] <= 2 * ((big + 255) // 256 * 256)
     for k, (p, s, t) in enumerate(reqs):
         np.testing.assert_array_equal(res[k], plain(osc, ctx, ds[s], p, t))
+    check = OracleCheck(osc, ctx, samples, ds)
+    for k in (0, 1):                               # one request of each tier
+        p, s, t = reqs[k]
+        check(res[k], p, s, t, f"budget-bound request {k}")
 
 
 def test_server_refusals(osc, ctx, resident):
@@ -106,6 +159,12 @@ def test_server_refusals(osc, ctx, resident):
         st = server.stats()
         assert st["rejected"] == refused
         assert st["max_queued"] <= 2
+        server.reset_stats()
+        st = server.stats()
+        assert st["submitted"] == st["completed"] == st["rejected"] == st["max_queued"] == 0
+        server.wait(server.submit(workload.TABLE1, 0, 0))
+        st = server.stats()
+        assert st["submitted"] == st["completed"] == st["max_in_flight"] == 1
     finally:
         server.close()
 
@@ -122,9 +181,11 @@ def test_server_poisson_stream(osc, ctx, resident):
         server.close()
     assert summ["stats"]["completed"] == 200
     assert 0 < summ["p50_ms"] <= summ["p99_ms"]
-    for k in (0, 57, 199):
+    check = OracleCheck(osc, ctx, samples, ds)
+    for k in (0, 57, 120, 199):
         p, s, t = reqs[k]
         np.testing.assert_array_equal(res[k], plain(osc, ctx, ds[s], p, t))
+        check(res[k], p, s, t, f"stream request {k}")
 
 
 def test_server_likelihood_and_mcmc(osc, ctx, resident):

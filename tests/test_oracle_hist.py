@@ -167,6 +167,21 @@ def test_vectorised_bin_rule_matches_oracle():
     np.testing.assert_array_equal(bins_np(x2, 0.5, 9.5, 37), oracle.bin_indices(x2, 0.5, 9.5, 37))
 
 
+def test_batched_bin_loop_equals_scalar_rule():
+    """The one-call form of the bin rule gives, element by element, what
+    the scalar rule gives (edges, their neighbours, NaN, infinities, -0.0,
+    with and without an energy scale)."""
+    lo, hi, nb = 0.0, 3.0, 50
+    wb = (hi - lo) / nb
+    edges = np.arange(-2, nb + 3) * wb
+    x = np.concatenate([edges, np.nextafter(edges, np.inf), np.nextafter(edges, -np.inf),
+                        [np.nan, np.inf, -np.inf, -0.0, 1e300, -1e300, 5e-324],
+                        np.random.default_rng(3).uniform(-0.5, 3.5, 3000)])
+    for es in (0.0, 0.013, -0.021):
+        want = [oracle.bin_index_scaled(v, lo, hi, nb, e_scale=es) for v in x]
+        np.testing.assert_array_equal(oracle.bin_indices(x, lo, hi, nb, e_scale=es), want)
+
+
 # ---------------------------------------------------------------- Eq. (2)
 def test_poisson_nll_matches_library_logpmf():
     import scipy.stats
