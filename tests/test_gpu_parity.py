@@ -14,6 +14,7 @@ Tolerances:
   * osc_fill_pdf's histogram is bit-identical to osc_fill_hist applied to
     its own per-event P (the reduction is the same), run to run.
 """
+import ctypes
 import numpy as np
 import pytest
 
@@ -537,8 +538,14 @@ def test_invalid_arguments_raise(osc, ctx):
         ctx.osc_fill_pdf(s, 1, 50, 0.0, 3.0, h)          # no such set
     with pytest.raises(osc.OscError):
         ctx.osc_fill_pdf(s, 0, 50, 3.0, 3.0, h)          # empty range
-    with pytest.raises(osc.OscError):
-        ctx.osc_fill_pdf(s, 0, 0, 0.0, 3.0, h)           # no bins
+    with pytest.raises(ValueError):
+        ctx.osc_fill_pdf(s, 0, 0, 0.0, 3.0, h)           # no bins: the binding refuses
+    # ... and so does the C ABI itself
+    cs = s.c_struct()
+    b = osc.osc_binning(0, 0.0, 3.0, 0.0)
+    assert osc.load().osc_fill_pdf(ctx.handle, ctypes.byref(cs), 0, ctypes.byref(b), 0,
+                                   ctypes.c_void_p(h.data_ptr()), None, None) \
+        == osc.OSC_ERR_INVALID_ARG
     with pytest.raises(osc.OscError):
         ctx.osc_reweight(s, -1, p)
     bad = osc.DeviceSample(s.e_true, s.flags, s.weight, s.e_reco, L_km=-1.0)
