@@ -25,6 +25,7 @@
 #ifndef OSC_H
 #define OSC_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -36,7 +37,7 @@ typedef enum {
     OSC_ERR_INVALID_ARG = 1,   /* a NULL pointer, a value outside its domain */
     OSC_ERR_OUT_OF_MEMORY = 2, /* device scratch could not be allocated      */
     OSC_ERR_DEVICE = 3,        /* no usable GPU, or a HIP runtime failure     */
-    OSC_ERR_BUDGET = 4,        /* reserved: over a memory budget              */
+    OSC_ERR_BUDGET = 4,        /* over a memory budget or a fixed capacity    */
     OSC_ERR_NOT_READY = 5      /* reserved: result not available yet          */
 } osc_status;
 
@@ -158,6 +159,28 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
 osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         const osc_binning* binning, osc_precision precision,
                         double* hist_out, double* p_out, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * osc_fill_pdf with the same arguments, kernels and results (bit for bit),
+ * that keeps its tile results and merge buffers in a fixed array of
+ * OSC_NOALLOC_SCRATCH_BYTES of device memory inside the library instead of
+ * the context's scratch.  It calls no hipMalloc, hipFree or other
+ * allocating routine.  The array's address on a device is resolved once,
+ * by osc_create on that device; each GPU holds its own array until the
+ * process ends.  Bytes needed: 8 (nbins + 2) (R + 2 S), with
+ * R = 128 ceil(T / 128) rows of tile results for T = ceil(n / 1024) tiles,
+ * and S = 0 for T <= 16384, else S = 128 ceil(ceil(T / 16384) / 128)
+ * (about 8 MiB for 2e7 events at 50 bins); larger requests return
+ * OSC_ERR_BUDGET before anything is enqueued.  Every call on a GPU, from
+ * any context, shares that GPU's array: calls whose work overlaps on the
+ * device (different streams, or other threads) race and give undefined
+ * histograms; calls ordered on one stream are safe.  Nothing in the array
+ * needs to start at zero: every call writes what it reads. */
+#define OSC_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+osc_status osc_fill_pdf_noalloc(osc_ctx* ctx, const osc_sample* sample, int32_t set,
+                                const osc_binning* binning, osc_precision precision,
+                                double* hist_out, double* p_out, void* stream);
 
 /* The reduction of osc_fill_pdf on given per-event values: histogram of
  * e_reco with contributions c = weight * value (separately rounded), same

@@ -144,8 +144,9 @@ struct osc_ctx {
     int32_t max_nbins = 0;
     std::vector<osc_params> params;
     std::vector<osc::SetConsts> consts;
-    Scratch scratch[kScratchSlots];
-    int next_scratch = 0;
+    Scratch slots[kScratchSlots];
+    int next_slot = 0;
+    double* noalloc = nullptr;      // this device's address of the static scratch array
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::mutex mu;
@@ -193,8 +194,8 @@ void prof_mark(hipEvent_t ev, hipStream_t stream)
 // its event); on the same stream the stream order already does.
 osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scratch** out)
 {
-    Scratch& s = ctx->scratch[ctx->next_scratch];
-    ctx->next_scratch = (ctx->next_scratch + 1) % kScratchSlots;
+    Scratch& s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kScratchSlots;
     if (s.done == nullptr && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return OSC_ERR_DEVICE;
     if (s.cap < bytes) {
@@ -292,7 +293,7 @@ size_t osc::host::fill_scratch_bytes(int64_t n, int nbins)
 }
 
 hipError_t osc::host::enqueue_fill(const osc::SetConsts& sc, const osc_sample* sample,
-                                   const osc_binning* binning, bool mixed, double* scratch,
+                                   const osc_binning* binning, bool mixed, double* partials,
                                    double* hist_out, double* p_out, hipStream_t stream)
 {
     const osc::BinConsts bc = bin_consts(binning);
@@ -300,8 +301,8 @@ hipError_t osc::host::enqueue_fill(const osc::SetConsts& sc, const osc_sample* s
     const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
     hipError_t e = osc::launch_tiles(1, p_out != nullptr, mixed, sc, path_consts(sample), bc,
                                      sample->n, sample->e_true, sample->flags, sample->weight,
-                                     sample->e_reco, nullptr, p_out, scratch, stream);
-    if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
+                                     sample->e_reco, nullptr, p_out, partials, stream);
+    if (e == hipSuccess) e = osc::launch_merge(plan, 1, partials, hist_out, stream);
     return e;
 }
 
@@ -313,31 +314,80 @@ using osc::host::path_consts;
 using osc::host::sample_ok;
 using osc::host::set_consts;
 
-// Tile partials + merge for one histogram on `stream`.
+// The per-event kernel and the merge of one histogram on `stream`, with
+// the tile results and level buffers in `partials` (merge_scratch_bytes of
+// `plan`).  t0 / t1 (nullable) receive the per-event kernel's own begin and
+// end times.
+hipError_t enqueue_hist(int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
+                        const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
+                        const double* e_true, const uint8_t* flags, const double* weight,
+                        const double* e_reco, const double* value, double* p_out,
+                        double* hist_out, const osc::MergePlan& plan, double* partials,
+                        hipStream_t stream, const osc::LayerPath* lp, hipEvent_t t0,
+                        hipEvent_t t1)
+{
+    hipError_t e = lp ? osc::launch_layered_tiles(mode, write_p, sc, *lp, bc, n, e_true, flags,
+                                                  weight, e_reco, p_out, partials, stream, t0,
+                                                  t1)
+                      : osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags,
+                                          weight, e_reco, value, p_out, partials, stream, t0,
+                                          t1);
+    if (e == hipSuccess) e = osc::launch_merge(plan, 1, partials, hist_out, stream);
+    return e;
+}
+
+// Tile partials + merge for one histogram on `stream`, in a scratch slot of
+// the context.
 osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
                     const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
                     const double* e_true, const uint8_t* flags, const double* weight,
                     const double* e_reco, const double* value, double* p_out,
                     double* hist_out, hipStream_t stream, const osc::LayerPath* lp = nullptr)
 {
-    const int nbt = bc.nb + 2;
     const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
-    const osc::MergePlan plan = osc::plan_merge(&tiles, 1, nbt);
+    const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
     Scratch* s = nullptr;
     osc_status st = acquire_scratch(ctx, osc::merge_scratch_bytes(plan, 1), stream, &s);
     if (st != OSC_OK) return st;
-    double* scratch = static_cast<double*>(s->ptr);
     ProfRec* pr = prof_begin(ctx, stream);
-    hipEvent_t t0 = pr ? pr->start : nullptr, t1 = pr ? pr->mid : nullptr;
-    hipError_t e = lp ? osc::launch_layered_tiles(mode, write_p, sc, *lp, bc, n, e_true, flags,
-                                                  weight, e_reco, p_out, scratch, stream, t0, t1)
-                      : osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags,
-                                          weight, e_reco, value, p_out, scratch, stream, t0, t1);
-    if (e == hipSuccess) e = osc::launch_merge(plan, 1, scratch, hist_out, stream);
+    const hipError_t e = enqueue_hist(mode, write_p, mixed, sc, pc, bc, n, e_true, flags, weight,
+                                      e_reco, value, p_out, hist_out, plan,
+                                      static_cast<double*>(s->ptr), stream, lp,
+                                      pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) prof_mark(pr->end, stream);
     st = release_scratch(s, stream);
     if (e != hipSuccess) return OSC_ERR_DEVICE;
     return st;
+}
+
+// ---- The entry point that allocates nothing --------------------------------
+// osc_fill_pdf_noalloc keeps its tile results and merge level buffers in
+// this file-scope array instead of a scratch slot of the context.  Each GPU
+// the library runs on holds its own copy for the life of the process.  In
+// host code the name stands for a host-side shadow, not a device address:
+// kernels are only ever given the address that hipGetSymbolAddress returns
+// for the current device (noalloc_address).
+static __device__ __align__(256) double scratch[OSC_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, which must be current;
+// resolved once per device.  nullptr when the runtime cannot resolve it.
+double* noalloc_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_noalloc_ptr[device] = static_cast<double*>(ptr);
+    }
+    return g_noalloc_ptr[device];
 }
 
 }  // namespace
@@ -357,6 +407,7 @@ osc_status osc_create(osc_ctx** out, int device)
     osc_ctx* ctx = new (std::nothrow) osc_ctx();
     if (!ctx) return OSC_ERR_OUT_OF_MEMORY;
     ctx->device = device;
+    ctx->noalloc = noalloc_address(device);
     // per-wave histograms: (nbins + 2) x kHistLanes accumulators x 8 B of
     // dynamic LDS, next to the static tables (channels, flags, sin/cos)
     const size_t static_lds = sizeof(osc::TileTables);
@@ -383,7 +434,7 @@ osc_status osc_destroy(osc_ctx* ctx)
     osc_status st = OSC_OK;
     (void)hipSetDevice(ctx->device);
     drop_profile(ctx);
-    for (Scratch& s : ctx->scratch) {
+    for (Scratch& s : ctx->slots) {
         if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
         if (s.ptr && hipFree(s.ptr) != hipSuccess) st = OSC_ERR_DEVICE;
         if (s.done && hipEventDestroy(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
@@ -453,6 +504,29 @@ osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                     path_consts(sample),
                     bin_consts(binning), sample->n, sample->e_true, sample->flags, sample->weight,
                     sample->e_reco, nullptr, p_out, hist_out, static_cast<hipStream_t>(stream));
+}
+
+osc_status osc_fill_pdf_noalloc(osc_ctx* ctx, const osc_sample* sample, int32_t set,
+                                const osc_binning* binning, osc_precision precision,
+                                double* hist_out, double* p_out, void* stream)
+{
+    if (!ctx || !sample_ok(sample, true) || !hist_out) return OSC_ERR_INVALID_ARG;
+    if (!binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
+    if (precision != OSC_FP64 && precision != OSC_FP32_MIXED) return OSC_ERR_INVALID_ARG;
+    const osc::BinConsts bc = bin_consts(binning);
+    const int64_t tiles = (sample->n + osc::kTileEvents - 1) / osc::kTileEvents;
+    const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
+    if (osc::merge_scratch_bytes(plan, 1) > OSC_NOALLOC_SCRATCH_BYTES) return OSC_ERR_BUDGET;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (!ctx->noalloc) return OSC_ERR_DEVICE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const hipError_t e = enqueue_hist(
+        1, p_out != nullptr, precision == OSC_FP32_MIXED, ctx->consts[size_t(set)],
+        path_consts(sample), bc, sample->n, sample->e_true, sample->flags, sample->weight,
+        sample->e_reco, nullptr, p_out, hist_out, plan, ctx->noalloc,
+        static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr);
+    return device_status(e);
 }
 
 namespace {

@@ -14,7 +14,6 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
-#include <vector>
 
 #include "osc_device.h"
 #include "osc_host_common.h"
@@ -243,18 +242,24 @@ hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
     return hipGetLastError();
 }
 
+// A level divides every sample's row count by kMergeChunkRows (rounding
+// up), so two levels reduce the largest accepted sample to one row.
+static_assert(kMaxEvents / kTileEvents <= kMergeChunkRows * kMergeChunkRows &&
+                  kMaxMergeLevels >= 2,
+              "the merge plan's level capacity covers every accepted sample");
+
 MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt)
 {
     auto align = [](int64_t r) { return (r + kLayoutChunk - 1) / kLayoutChunk * kLayoutChunk; };
     MergePlan p;
     p.nbt = nbt;
     p.n_samples = n_samples;
-    std::vector<int64_t> rows(tiles, tiles + n_samples);
-    std::vector<int64_t> row0(static_cast<size_t>(n_samples), 0);
+    int64_t rows[kMaxBatchSamples], row0[kMaxBatchSamples];
     int64_t in_rows = 0;
     for (int s = 0; s < n_samples; ++s) {
-        row0[size_t(s)] = in_rows;
-        in_rows += align(rows[size_t(s)]);
+        rows[s] = tiles[s];
+        row0[s] = in_rows;
+        in_rows += align(rows[s]);
     }
     int64_t level_max = 0;
     for (bool first = true;; first = false) {
@@ -264,17 +269,17 @@ MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt)
         int64_t chunks = 0, out_rows = 0;
         bool final_level = true;
         for (int s = 0; s < n_samples; ++s) {
-            const int64_t r = rows[size_t(s)];
+            const int64_t r = rows[s];
             const int64_t ch = r > kMergeChunkRows ? (r + kMergeChunkRows - 1) / kMergeChunkRows : 1;
             L.rows[s] = r;
-            L.in_row0[s] = row0[size_t(s)];
+            L.in_row0[s] = row0[s];
             L.chunk0[s] = chunks;
             L.out_row0[s] = out_rows;
             chunks += ch;
             out_rows += align(ch);
             if (ch > 1) final_level = false;
-            rows[size_t(s)] = ch;
-            row0[size_t(s)] = L.out_row0[s];
+            rows[s] = ch;
+            row0[s] = L.out_row0[s];
         }
         L.total_chunks = chunks;
         L.set_stride_in = in_rows * nbt;
@@ -282,7 +287,7 @@ MergePlan plan_merge(const int64_t* tiles, int n_samples, int nbt)
         if (first) p.tile_set_stride = L.set_stride_in;
         else level_max = std::max(level_max, L.set_stride_in);
         if (!final_level) level_max = std::max(level_max, L.set_stride_out);
-        p.levels.push_back(L);
+        p.levels[p.n_levels++] = L;
         in_rows = out_rows;
         if (final_level) break;
     }
@@ -301,10 +306,10 @@ hipError_t launch_merge(const MergePlan& p, int64_t n_sets, double* scratch, dou
     double* bufs[2] = {scratch + n_sets * p.tile_set_stride,
                        scratch + n_sets * (p.tile_set_stride + p.level_set_stride)};
     const double* in = scratch;
-    for (size_t l = 0; l < p.levels.size(); ++l) {
+    for (int l = 0; l < p.n_levels; ++l) {
         const MergeLevel& L = p.levels[l];
         const dim3 grid{unsigned(L.total_chunks), unsigned(p.nbt), unsigned(n_sets)};
-        const bool final_level = l + 1 == p.levels.size();
+        const bool final_level = l + 1 == p.n_levels;
         double* out = final_level ? hist_out : bufs[l % 2];
         if (final_level)
             hipLaunchKernelGGL(merge_level_kernel<true>, grid, dim3(kMergeThreads), 0, stream, L,

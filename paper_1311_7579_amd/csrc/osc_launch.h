@@ -1,8 +1,6 @@
 // Kernel launchers of libosc (defined in osc_kernels.hip).
 #pragma once
 
-#include <vector>
-
 #include "osc_internal.h"
 
 namespace osc {
@@ -29,11 +27,16 @@ hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,
                                 hipEvent_t ev_end = nullptr);
 
 // The levels of the histogram merge for n_samples samples of tiles[s]
-// tiles each (per parameter set), and the scratch strides they need.
+// tiles each (per parameter set), and the scratch strides they need.  A
+// fixed-capacity value: planning a merge allocates nothing.  A sample has
+// at most kMaxEvents / kTileEvents = 2^22 tiles, which two levels of
+// kMergeChunkRows = 2^14 rows reduce to one.
+constexpr int kMaxMergeLevels = 3;
 struct MergePlan {
     int nbt = 0;
     int n_samples = 0;
-    std::vector<MergeLevel> levels;
+    int n_levels = 0;
+    MergeLevel levels[kMaxMergeLevels];
     int64_t tile_set_stride = 0;   // elements of tile results per set
     int64_t level_set_stride = 0;  // elements of each of the two level buffers per set
 };

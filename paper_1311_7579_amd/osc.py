@@ -24,6 +24,8 @@ OSC_ERR_NOT_READY = 5
 
 OSC_FP64 = 0
 OSC_FP32_MIXED = 1
+# device scratch of osc_fill_pdf_noalloc (include/osc.h)
+OSC_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 PARAM_FIELDS = ("sin2_th12", "sin2_th23", "sin2_th13", "dm2_32", "dm2_21", "delta_cp")
 
@@ -115,6 +117,8 @@ def load():
     L.osc_fill_pdf.argtypes = [vp, ctypes.POINTER(osc_sample), i32, ctypes.POINTER(osc_binning),
                                ctypes.c_int, vp, vp, vp]
     L.osc_fill_pdf.restype = st
+    L.osc_fill_pdf_noalloc.argtypes = L.osc_fill_pdf.argtypes
+    L.osc_fill_pdf_noalloc.restype = st
     L.osc_fill_hist.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(osc_binning), vp, vp]
     L.osc_fill_hist.restype = st
     L.osc_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -405,6 +409,21 @@ class Context:
         _check(load().osc_fill_pdf(self.handle, ctypes.byref(cs), int(set_index), ctypes.byref(b),
                                    int(precision), hp, pp, _stream(stream)),
                "osc_fill_pdf")
+
+    def osc_fill_pdf_noalloc(self, sample: DeviceSample, set_index, nbins, lo, hi, hist_out,
+                             p_out=None, precision=OSC_FP64, stream=None, e_scale=0.0):
+        """osc_fill_pdf without device allocation: the library's fixed
+        scratch array (OSC_NOALLOC_SCRATCH_BYTES per GPU) holds the tile
+        results; calls that overlap on one GPU race."""
+        cs = self._sample(sample, True)
+        hp, pp = device_vecs(self._hist(hist_out, nbins),
+                             (p_out, "p_out", "float64", dict(n=sample.n, optional=True)),
+                             device=self.device)
+        b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
+        _check(load().osc_fill_pdf_noalloc(self.handle, ctypes.byref(cs), int(set_index),
+                                           ctypes.byref(b), int(precision), hp, pp,
+                                           _stream(stream)),
+               "osc_fill_pdf_noalloc")
 
     def osc_validate_sample(self, sample: DeviceSample, stream=None):
         """(events with a true energy that is not finite and > 0, events with
