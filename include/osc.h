@@ -160,6 +160,38 @@ osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         const osc_binning* binning, osc_precision precision,
                         double* hist_out, double* p_out, void* stream);
 
+/* ---- Cached reco-energy bins (Sec. 1.1.1) ----
+ * Event-by-event reweighting changes only the weights w * P of the events;
+ * the bin of each event's reconstructed energy stays the same from one
+ * parameter set to the next.  A binned sample computes it once: for every
+ * event the histogram slot its contribution goes to (the bin by the rule
+ * of osc_binning, and the event's accumulator in the reduction contract),
+ * 2 bytes of device memory per event.  osc_fill_pdf_binned then reads
+ * those 2 bytes instead of the 8-byte reco energy and skips the bin
+ * arithmetic; its results are bit-identical to osc_fill_pdf with the same
+ * sample and binning. */
+typedef struct osc_binned osc_binned;
+
+/* Bin `sample` (device arrays as in osc_sample; e_reco is read here and
+ * never again; e_true, flags and weight must stay valid and unchanged for
+ * the life of the binned sample) under `binning` (e_scale included; a
+ * different shift needs its own binned sample).  Allocates n 16-bit
+ * entries of device memory owned by the binned sample.  Synchronous: waits
+ * for all earlier work on the device, returns once the bins are on it. */
+osc_status osc_binned_create(osc_ctx* ctx, const osc_sample* sample,
+                             const osc_binning* binning, osc_binned** out);
+
+/* Wait for the device and free the binned sample. NULL is accepted. */
+osc_status osc_binned_destroy(osc_binned* binned);
+
+/* osc_fill_pdf on a binned sample of the same context (the binning and
+ * path are the binned sample's): hist_out (device, nbins + 2 FP64
+ * entries) and p_out (device, n entries, nullable) as for osc_fill_pdf,
+ * with the same bits. */
+osc_status osc_fill_pdf_binned(osc_ctx* ctx, const osc_binned* binned, int32_t set,
+                               osc_precision precision, double* hist_out, double* p_out,
+                               void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * osc_fill_pdf with the same arguments, kernels and results (bit for bit),
@@ -312,9 +344,12 @@ typedef struct {
 } osc_batch_config;
 
 /* Prepare a batched evaluation over n_samples (1..16) resident samples
- * (device arrays as in osc_sample; they must stay valid and unchanged for
- * the life of the batch), one binning and one precision, for up to max_sets
- * (1..65535) parameter sets per run.  Allocates the device scratch (tile results of
+ * (device arrays as in osc_sample; e_true, flags and weight must stay valid
+ * and unchanged for the life of the batch; e_reco is read only here, where
+ * every event's histogram slot is cached as for osc_binned_create, 2 bytes
+ * per event), one binning and one precision, for up to max_sets
+ * (1..65535) parameter sets per run.  Synchronous (waits for earlier work
+ * on the device).  Allocates the device scratch (tile results of
  * max_sets sets) and chooses a default configuration.  OSC_ERR_INVALID_ARG
  * also when max_sets x (the samples' tiles of 1024 events) work items
  * would overflow the 32-bit work counter of the persistent schedules. */
@@ -373,9 +408,13 @@ typedef struct {
 } osc_server_stats;
 
 /* Start a server over n_samples resident samples (device arrays as in
- * osc_sample, valid and unchanged for the server's life) and one binning.
- * Allocates the scratch budget, the slot streams and pinned result buffers,
- * and starts the dispatcher thread. */
+ * osc_sample; e_true, flags and weight valid and unchanged for the
+ * server's life; e_reco is read only here, where every event's histogram
+ * slot is cached as for osc_binned_create) and one binning.  Synchronous
+ * (waits for earlier work on the device).  Allocates the bin caches (2
+ * bytes per event, outside the scratch budget), the scratch budget, the
+ * slot streams and pinned result buffers, and starts the dispatcher
+ * thread. */
 osc_status osc_server_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_samples,
                              const osc_binning* binning, const osc_server_config* cfg,
                              osc_server** out);

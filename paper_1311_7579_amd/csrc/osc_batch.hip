@@ -34,7 +34,7 @@ struct BatchSampleDev {
     const double* e_true;
     const uint8_t* flags;
     const double* weight;
-    const double* e_reco;
+    const uint16_t* bins;   // cached histogram slots (made at batch creation)
     int64_t n;
     int64_t tile0;   // first work tile of this sample among all samples
     int64_t row0;    // first tile row of this sample in a set's tile-result region
@@ -92,7 +92,7 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
         while (s + 1 < a.n_samples && gtile >= samples[s + 1].tile0) ++s;
         const BatchSampleDev& S = samples[s];
         const int64_t tile = gtile - S.tile0;
-        const TileArrays t = tile_arrays(tile, S.n, S.e_true, S.flags, S.weight, S.e_reco,
+        const TileArrays t = tile_arrays(tile, S.n, S.e_true, S.flags, S.weight, nullptr, S.bins,
                                          nullptr, nullptr);
         const int set_end = int(min(int64_t(a.n_sets), (g + 1) * a.sets_per_item));
         for (int set = int(g) * a.sets_per_item; set < set_end; ++set) {
@@ -103,13 +103,13 @@ void batch_kernel(BatchArgs a, SinCosTable sctab,
             __syncthreads();
             const ConstDensityProb<MIXED> prob{&sc, &tabs, S.pc.kA, S.pc.kL};
             if (t.n == kTileEvents)
-                tile_events<kPdf, false, true, true, false>(prob, a.bc, hist, lane, t.n, t.e_true,
-                                                       t.flags, t.weight, t.e_reco, nullptr,
-                                                       nullptr);
+                tile_events<kPdfBinned, false, true, true, false>(
+                    prob, a.bc, hist, lane, t.n, t.e_true, t.flags, t.weight, nullptr, t.bins,
+                    nullptr, nullptr);
             else
-                tile_events<kPdf, false, false, true, false>(prob, a.bc, hist, lane, t.n, t.e_true,
-                                                        t.flags, t.weight, t.e_reco, nullptr,
-                                                        nullptr);
+                tile_events<kPdfBinned, false, false, true, false>(
+                    prob, a.bc, hist, lane, t.n, t.e_true, t.flags, t.weight, nullptr, t.bins,
+                    nullptr, nullptr);
             __syncthreads();
             tile_write(hist, lane, nbt, S.row0 + tile, partial + int64_t(set) * a.set_stride);
         }
@@ -130,6 +130,7 @@ struct osc_batch {
     std::vector<int64_t> tiles;
     osc::MergePlan plan;
     osc::BatchSampleDev* d_samples = nullptr;
+    uint16_t* d_bins = nullptr;   // the samples' cached histogram slots, back to back
     osc::SetConsts* d_sets = nullptr;
     osc::SetConsts* h_sets = nullptr;   // pinned staging
     hipEvent_t staged = nullptr;
@@ -275,7 +276,7 @@ void free_batch(osc_batch* b)
     if (b->h_sets) (void)hipHostFree(b->h_sets);
     for (void* p : {static_cast<void*>(b->d_samples), static_cast<void*>(b->d_sets),
                     static_cast<void*>(b->d_scratch), static_cast<void*>(b->d_queue),
-                    static_cast<void*>(b->d_hist)})
+                    static_cast<void*>(b->d_hist), static_cast<void*>(b->d_bins)})
         if (p) (void)hipFree(p);
     delete b;
 }
@@ -358,7 +359,7 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
         const int64_t t = (samples[s].n + osc::kTileEvents - 1) / osc::kTileEvents;
         b->tiles.push_back(t);
         hs[size_t(s)] = osc::BatchSampleDev{samples[s].e_true, samples[s].flags, samples[s].weight,
-                                            samples[s].e_reco, samples[s].n, tile0, 0,
+                                            nullptr, samples[s].n, tile0, 0,
                                             osc::host::path_consts(&samples[s])};
         tile0 += t;
     }
@@ -390,6 +391,29 @@ osc_status osc_batch_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_s
     if (!launchable(b, max_sets, osc_batch_config{1, osc::kDynamic, 0, 1})) {
         free_batch(b);
         return OSC_ERR_INVALID_ARG;
+    }
+
+    // Only now, with every argument accepted, are the sample arrays read:
+    // the reco-energy bins do not change from run to run, so each event's
+    // histogram slot is cached once, here.
+    int64_t events = 0;
+    for (int s = 0; s < n_samples; ++s) events += samples[s].n;
+    if (events > 0 && hipMalloc(&b->d_bins, size_t(events) * sizeof(uint16_t)) != hipSuccess) {
+        free_batch(b);
+        return OSC_ERR_OUT_OF_MEMORY;
+    }
+    hipError_t be = hipDeviceSynchronize();
+    events = 0;
+    for (int s = 0; s < n_samples && be == hipSuccess; ++s) {
+        uint16_t* bins = samples[s].n > 0 ? b->d_bins + events : nullptr;
+        hs[size_t(s)].bins = bins;
+        be = osc::host::enqueue_bin_slots(&samples[s], binning, bins, nullptr);
+        events += samples[s].n;
+    }
+    if (be == hipSuccess) be = hipDeviceSynchronize();
+    if (be != hipSuccess) {
+        free_batch(b);
+        return OSC_ERR_DEVICE;
     }
 
     const size_t scratch = osc::merge_scratch_bytes(b->plan, max_sets);

@@ -456,13 +456,20 @@ __device__ __forceinline__ double lane_tree(const double* h, int bin)
     }
 }
 
-enum Mode { kReweight = 0, kPdf = 1, kHist = 2 };
+// kPdfBinned: kPdf with the events' histogram slots read from a cached
+// per-sample array (one 16-bit LDS slot index per event, see bin_slot)
+// instead of computed from the reco energy.
+enum Mode { kReweight = 0, kPdf = 1, kHist = 2, kPdfBinned = 3 };
+
+constexpr bool reads_bins(int mode) { return mode == kPdfBinned; }
+constexpr bool has_hist(int mode) { return mode != kReweight; }
 
 struct EventIn {
-    double e;     // true energy (or the given value in kHist mode)
+    double e;       // true energy (or the given value in kHist mode)
     double w;
-    double x;
+    double x;       // reco energy (kPdf, kHist)
     uint32_t f;
+    uint32_t slot;  // cached histogram slot (kPdfBinned)
 };
 
 // The arrays of one tile as raw buffer resources (base in SGPRs, size in
@@ -482,8 +489,8 @@ struct TileBufs {
 template <int MODE>
 __device__ __forceinline__ TileBufs tile_bufs(uint32_t n, const double* e_true,
                                               const uint8_t* flags, const double* weight,
-                                              const double* e_reco, const double* value,
-                                              double* p_out)
+                                              const double* e_reco, const uint16_t* bins,
+                                              const double* value, double* p_out)
 {
     const int nb = int(n * sizeof(double));
     TileBufs b;
@@ -491,7 +498,11 @@ __device__ __forceinline__ TileBufs tile_bufs(uint32_t n, const double* e_true,
         const_cast<double*>(MODE == kHist ? value : e_true), 0, nb, kBufDword3);
     b.f = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(flags), 0, int(n), kBufDword3);
     b.w = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(weight), 0, nb, kBufDword3);
-    b.x = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(e_reco), 0, nb, kBufDword3);
+    if constexpr (reads_bins(MODE))
+        b.x = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(bins), 0,
+                                                int(n * sizeof(uint16_t)), kBufDword3);
+    else
+        b.x = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(e_reco), 0, nb, kBufDword3);
     b.p = __builtin_amdgcn_make_buffer_rsrc(p_out, 0, nb, kBufDword3);
     return b;
 }
@@ -509,15 +520,17 @@ struct TilePtrs {
     const uint8_t* f;
     const double* w;
     const double* x;
+    const uint16_t* s;
     double* p;
 };
 
 template <int MODE>
 __device__ __forceinline__ TilePtrs tile_ptrs(const double* e_true, const uint8_t* flags,
                                               const double* weight, const double* e_reco,
-                                              const double* value, double* p_out)
+                                              const uint16_t* bins, const double* value,
+                                              double* p_out)
 {
-    return TilePtrs{MODE == kHist ? value : e_true, flags, weight, e_reco, p_out};
+    return TilePtrs{MODE == kHist ? value : e_true, flags, weight, e_reco, bins, p_out};
 }
 
 template <int MODE, bool FULL>
@@ -529,8 +542,9 @@ __device__ __forceinline__ EventIn load_event(const TilePtrs& b, uint32_t l, uin
     const bool in = FULL || i < n;
     v.e = in ? b.e[i] : 1.0;
     v.f = (MODE != kHist && in) ? uint32_t(b.f[i]) : 0u;
-    v.w = (MODE != kReweight && in) ? b.w[i] : 0.0;
-    v.x = (MODE != kReweight && in) ? b.x[i] : 0.0;
+    v.w = (has_hist(MODE) && in) ? b.w[i] : 0.0;
+    v.x = (has_hist(MODE) && !reads_bins(MODE) && in) ? b.x[i] : 0.0;
+    v.slot = (reads_bins(MODE) && in) ? uint32_t(b.s[i]) : 0u;
     return v;
 }
 
@@ -551,8 +565,11 @@ __device__ __forceinline__ EventIn load_event(const TileBufs& b, uint32_t l, uin
     v.e = in ? buf_load_f64(b.e, l8, g8) : 1.0;
     v.f = (MODE != kHist && in) ? uint32_t(__builtin_amdgcn_raw_buffer_load_b8(b.f, l, g0, 0))
                                 : 0u;
-    v.w = (MODE != kReweight && in) ? buf_load_f64(b.w, l8, g8) : 0.0;
-    v.x = (MODE != kReweight && in) ? buf_load_f64(b.x, l8, g8) : 0.0;
+    v.w = (has_hist(MODE) && in) ? buf_load_f64(b.w, l8, g8) : 0.0;
+    v.x = (has_hist(MODE) && !reads_bins(MODE) && in) ? buf_load_f64(b.x, l8, g8) : 0.0;
+    v.slot = (reads_bins(MODE) && in)
+                 ? uint32_t(__builtin_amdgcn_raw_buffer_load_b16(b.x, l * 2u, g0 * 2u, 0))
+                 : 0u;
     return v;
 }
 
@@ -570,12 +587,14 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
                                            int lane, uint32_t l, uint32_t g0, uint32_t n,
                                            const EventIn (&ev)[kGroup], const ARR& arr)
 {
+    constexpr bool kComputeBins = has_hist(MODE) && !reads_bins(MODE);
     double P[kGroup], k[kGroup];
     bool edge[kGroup];
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) {
         P[j] = (MODE != kHist) ? prob(ev[j].e, ev[j].f) : ev[j].e;
-        k[j] = (MODE != kReweight) ? bin_floor_fast(ev[j].x, bc, edge[j]) : 0.0;
+        edge[j] = false;
+        k[j] = kComputeBins ? bin_floor_fast(ev[j].x, bc, edge[j]) : 0.0;
     }
     if (WRITE_P) {
 #pragma unroll
@@ -590,7 +609,7 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
     bool any_edge = false;
 #pragma unroll
     for (int j = 0; j < kGroup; ++j) any_edge |= edge[j];
-    if (__builtin_expect(any_edge, 0)) {
+    if (kComputeBins && __builtin_expect(any_edge, 0)) {
 #pragma unroll
         for (int j = 0; j < kGroup; ++j)
             if (edge[j]) k[j] = bin_floor_exact(ev[j].x, bc);
@@ -600,7 +619,8 @@ __device__ __forceinline__ void tile_group(const PROB& prob, const BinConsts& bc
         if (FULL || l + g0 + j * kTileLanes < n) {
 #pragma clang fp contract(off)
             const double cval = ev[j].w * P[j];            // rounded, never fused
-            const int slot = hslot(lds_bin(k[j], bc), lane & (kHistLanes - 1));
+            const int slot = reads_bins(MODE) ? int(ev[j].slot)
+                                              : hslot(lds_bin(k[j], bc), lane & (kHistLanes - 1));
             // The lanes sharing an accumulator add in ascending lane order:
             // one masked LDS atomic add per lane group, group after group.
             // Within a group the lanes hit distinct accumulators, and the
@@ -632,16 +652,16 @@ template <int MODE, bool WRITE_P, bool FULL, bool ROLL, bool BUF = true, class P
 __device__ __forceinline__ void tile_events(const PROB& prob, const BinConsts& bc, double* hist,
                                             int lane, uint32_t n, const double* e_true,
                                             const uint8_t* flags, const double* weight,
-                                            const double* e_reco, const double* value,
-                                            double* p_out)
+                                            const double* e_reco, const uint16_t* bins,
+                                            const double* value, double* p_out)
 {
     constexpr int kGroups = kLaneEvents / kGroup;
     const uint32_t l = uint32_t(lane);
     const auto bufs = [&] {
         if constexpr (BUF)
-            return tile_bufs<MODE>(n, e_true, flags, weight, e_reco, value, p_out);
+            return tile_bufs<MODE>(n, e_true, flags, weight, e_reco, bins, value, p_out);
         else
-            return tile_ptrs<MODE>(e_true, flags, weight, e_reco, value, p_out);
+            return tile_ptrs<MODE>(e_true, flags, weight, e_reco, bins, value, p_out);
     }();
     if constexpr (ROLL) {
         EventIn cur[kGroup], nxt[kGroup];
@@ -697,6 +717,7 @@ struct TileArrays {
     const uint8_t* flags;
     const double* weight;
     const double* e_reco;
+    const uint16_t* bins;
     const double* value;
     double* p_out;
     uint32_t n;
@@ -704,8 +725,8 @@ struct TileArrays {
 
 __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const double* e_true,
                                                   const uint8_t* flags, const double* weight,
-                                                  const double* e_reco, const double* value,
-                                                  double* p_out)
+                                                  const double* e_reco, const uint16_t* bins,
+                                                  const double* value, double* p_out)
 {
     const int64_t t0 = tile * kTileEvents;
     TileArrays a;
@@ -713,6 +734,7 @@ __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const
     a.flags = flags ? flags + t0 : nullptr;
     a.weight = weight ? weight + t0 : nullptr;
     a.e_reco = e_reco ? e_reco + t0 : nullptr;
+    a.bins = bins ? bins + t0 : nullptr;
     a.value = value ? value + t0 : nullptr;
     a.p_out = p_out ? p_out + t0 : nullptr;
     a.n = uint32_t(min(n - t0, int64_t(kTileEvents)));

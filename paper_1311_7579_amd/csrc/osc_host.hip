@@ -293,17 +293,25 @@ size_t osc::host::fill_scratch_bytes(int64_t n, int nbins)
 }
 
 hipError_t osc::host::enqueue_fill(const osc::SetConsts& sc, const osc_sample* sample,
-                                   const osc_binning* binning, bool mixed, double* partials,
-                                   double* hist_out, double* p_out, hipStream_t stream)
+                                   const uint16_t* bins, const osc_binning* binning, bool mixed,
+                                   double* partials, double* hist_out, double* p_out,
+                                   hipStream_t stream)
 {
     const osc::BinConsts bc = bin_consts(binning);
     const int64_t tiles = (sample->n + osc::kTileEvents - 1) / osc::kTileEvents;
     const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
-    hipError_t e = osc::launch_tiles(1, p_out != nullptr, mixed, sc, path_consts(sample), bc,
-                                     sample->n, sample->e_true, sample->flags, sample->weight,
-                                     sample->e_reco, nullptr, p_out, partials, stream);
+    hipError_t e = osc::launch_tiles(bins ? 3 : 1, p_out != nullptr, mixed, sc,
+                                     path_consts(sample), bc, sample->n, sample->e_true,
+                                     sample->flags, sample->weight, bins ? nullptr : sample->e_reco,
+                                     bins, nullptr, p_out, partials, stream);
     if (e == hipSuccess) e = osc::launch_merge(plan, 1, partials, hist_out, stream);
     return e;
+}
+
+hipError_t osc::host::enqueue_bin_slots(const osc_sample* sample, const osc_binning* binning,
+                                        uint16_t* bins, hipStream_t stream)
+{
+    return osc::launch_bin_slots(sample->n, sample->e_reco, bin_consts(binning), bins, stream);
 }
 
 namespace {
@@ -321,17 +329,17 @@ using osc::host::set_consts;
 hipError_t enqueue_hist(int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
                         const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
                         const double* e_true, const uint8_t* flags, const double* weight,
-                        const double* e_reco, const double* value, double* p_out,
-                        double* hist_out, const osc::MergePlan& plan, double* partials,
-                        hipStream_t stream, const osc::LayerPath* lp, hipEvent_t t0,
-                        hipEvent_t t1)
+                        const double* e_reco, const uint16_t* bins, const double* value,
+                        double* p_out, double* hist_out, const osc::MergePlan& plan,
+                        double* partials, hipStream_t stream, const osc::LayerPath* lp,
+                        hipEvent_t t0, hipEvent_t t1)
 {
     hipError_t e = lp ? osc::launch_layered_tiles(mode, write_p, sc, *lp, bc, n, e_true, flags,
                                                   weight, e_reco, p_out, partials, stream, t0,
                                                   t1)
                       : osc::launch_tiles(mode, write_p, mixed, sc, pc, bc, n, e_true, flags,
-                                          weight, e_reco, value, p_out, partials, stream, t0,
-                                          t1);
+                                          weight, e_reco, bins, value, p_out, partials, stream,
+                                          t0, t1);
     if (e == hipSuccess) e = osc::launch_merge(plan, 1, partials, hist_out, stream);
     return e;
 }
@@ -341,8 +349,9 @@ hipError_t enqueue_hist(int mode, bool write_p, bool mixed, const osc::SetConsts
 osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc::SetConsts& sc,
                     const osc::PathConsts& pc, const osc::BinConsts& bc, int64_t n,
                     const double* e_true, const uint8_t* flags, const double* weight,
-                    const double* e_reco, const double* value, double* p_out,
-                    double* hist_out, hipStream_t stream, const osc::LayerPath* lp = nullptr)
+                    const double* e_reco, const uint16_t* bins, const double* value,
+                    double* p_out, double* hist_out, hipStream_t stream,
+                    const osc::LayerPath* lp = nullptr)
 {
     const int64_t tiles = (n + osc::kTileEvents - 1) / osc::kTileEvents;
     const osc::MergePlan plan = osc::plan_merge(&tiles, 1, bc.nb + 2);
@@ -351,7 +360,7 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
     if (st != OSC_OK) return st;
     ProfRec* pr = prof_begin(ctx, stream);
     const hipError_t e = enqueue_hist(mode, write_p, mixed, sc, pc, bc, n, e_true, flags, weight,
-                                      e_reco, value, p_out, hist_out, plan,
+                                      e_reco, bins, value, p_out, hist_out, plan,
                                       static_cast<double*>(s->ptr), stream, lp,
                                       pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) prof_mark(pr->end, stream);
@@ -481,7 +490,7 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set, dou
     const hipError_t e = osc::launch_tiles(0, true, false, ctx->consts[size_t(set)],
                                            path_consts(sample), bc,
                                            sample->n, sample->e_true, sample->flags, nullptr,
-                                           nullptr, nullptr, p_out, nullptr, hs,
+                                           nullptr, nullptr, nullptr, p_out, nullptr, hs,
                                            pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) {
         (void)hipEventDestroy(pr->end);
@@ -503,7 +512,8 @@ osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
     return run_hist(ctx, 1, p_out != nullptr, precision == OSC_FP32_MIXED, ctx->consts[size_t(set)],
                     path_consts(sample),
                     bin_consts(binning), sample->n, sample->e_true, sample->flags, sample->weight,
-                    sample->e_reco, nullptr, p_out, hist_out, static_cast<hipStream_t>(stream));
+                    sample->e_reco, nullptr, nullptr, p_out, hist_out,
+                    static_cast<hipStream_t>(stream));
 }
 
 osc_status osc_fill_pdf_noalloc(osc_ctx* ctx, const osc_sample* sample, int32_t set,
@@ -524,9 +534,77 @@ osc_status osc_fill_pdf_noalloc(osc_ctx* ctx, const osc_sample* sample, int32_t 
     const hipError_t e = enqueue_hist(
         1, p_out != nullptr, precision == OSC_FP32_MIXED, ctx->consts[size_t(set)],
         path_consts(sample), bc, sample->n, sample->e_true, sample->flags, sample->weight,
-        sample->e_reco, nullptr, p_out, hist_out, plan, ctx->noalloc,
+        sample->e_reco, nullptr, nullptr, p_out, hist_out, plan, ctx->noalloc,
         static_cast<hipStream_t>(stream), nullptr, nullptr, nullptr);
     return device_status(e);
+}
+
+struct osc_binned {
+    osc_ctx* ctx = nullptr;
+    osc_sample sample{};        // e_reco is not read after creation
+    osc_binning binning{};
+    uint16_t* slots = nullptr;  // n cached histogram slots (device)
+};
+
+osc_status osc_binned_create(osc_ctx* ctx, const osc_sample* sample, const osc_binning* binning,
+                             osc_binned** out)
+{
+    if (!out) return OSC_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!ctx || !sample_ok(sample, true) || !binning_ok(ctx, binning)) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    osc_binned* b = new (std::nothrow) osc_binned();
+    if (!b) return OSC_ERR_OUT_OF_MEMORY;
+    b->ctx = ctx;
+    b->sample = *sample;
+    b->binning = *binning;
+    if (sample->n > 0 &&
+        hipMalloc(&b->slots, size_t(sample->n) * sizeof(uint16_t)) != hipSuccess) {
+        delete b;
+        return OSC_ERR_OUT_OF_MEMORY;
+    }
+    // synchronous: after earlier work on the device (the caller's uploads),
+    // and the slots are ready on return
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = osc::host::enqueue_bin_slots(sample, binning, b->slots, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (b->slots) (void)hipFree(b->slots);
+        delete b;
+        return OSC_ERR_DEVICE;
+    }
+    *out = b;
+    return OSC_OK;
+}
+
+osc_status osc_binned_destroy(osc_binned* b)
+{
+    if (!b) return OSC_OK;
+    osc_status st = OSC_OK;
+    if (b->slots) {
+        if (hipSetDevice(b->ctx->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+            hipFree(b->slots) != hipSuccess)
+            st = OSC_ERR_DEVICE;
+    }
+    delete b;
+    return st;
+}
+
+osc_status osc_fill_pdf_binned(osc_ctx* ctx, const osc_binned* b, int32_t set,
+                               osc_precision precision, double* hist_out, double* p_out,
+                               void* stream)
+{
+    if (!ctx || !b || b->ctx != ctx || !hist_out) return OSC_ERR_INVALID_ARG;
+    if (precision != OSC_FP64 && precision != OSC_FP32_MIXED) return OSC_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (set < 0 || size_t(set) >= ctx->consts.size()) return OSC_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return OSC_ERR_DEVICE;
+    const osc_sample& s = b->sample;
+    return run_hist(ctx, 3, p_out != nullptr, precision == OSC_FP32_MIXED,
+                    ctx->consts[size_t(set)], path_consts(&s), bin_consts(&b->binning), s.n,
+                    s.e_true, s.flags, s.weight, nullptr, b->slots, nullptr, p_out, hist_out,
+                    static_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -593,7 +671,7 @@ osc_status osc_fill_pdf_layered(osc_ctx* ctx, const osc_sample* sample, const os
     const osc::LayerPath lp = layer_path(layers, n_layers);
     return run_hist(ctx, 1, p_out != nullptr, false, ctx->consts[size_t(set)], osc::PathConsts{},
                     bin_consts(binning), sample->n, sample->e_true, sample->flags,
-                    sample->weight, sample->e_reco, nullptr, p_out, hist_out,
+                    sample->weight, sample->e_reco, nullptr, nullptr, p_out, hist_out,
                     static_cast<hipStream_t>(stream), &lp);
 }
 
@@ -609,7 +687,7 @@ osc_status osc_fill_hist(osc_ctx* ctx, int64_t n, const double* value, const dou
     const osc::SetConsts sc{};
     const osc::PathConsts pc{0.0, 0.0};
     return run_hist(ctx, 2, false, false, sc, pc, bin_consts(binning), n, nullptr, nullptr, weight,
-                    e_reco, value, nullptr, hist_out, static_cast<hipStream_t>(stream));
+                    e_reco, nullptr, value, nullptr, hist_out, static_cast<hipStream_t>(stream));
 }
 
 osc_status osc_profile_enable(osc_ctx* ctx, int on)

@@ -25,11 +25,17 @@ bool ctx_set(osc_ctx* ctx, int32_t set, SetConsts* out);
 size_t fill_scratch_bytes(int64_t n, int nbins);
 
 // Enqueues the per-event kernel and the merge of one histogram on `stream`
-// with caller-provided scratch (fill_scratch_bytes).  Arguments are assumed
-// validated.
-hipError_t enqueue_fill(const SetConsts& sc, const osc_sample* sample, const osc_binning* binning,
-                        bool mixed, double* scratch, double* hist_out, double* p_out,
-                        hipStream_t stream);
+// with caller-provided scratch (fill_scratch_bytes).  With `bins` (the
+// sample's cached histogram slots for this binning, enqueue_bin_slots) the
+// reco energies are not read.  Arguments are assumed validated.
+hipError_t enqueue_fill(const SetConsts& sc, const osc_sample* sample, const uint16_t* bins,
+                        const osc_binning* binning, bool mixed, double* scratch,
+                        double* hist_out, double* p_out, hipStream_t stream);
+
+// Enqueues the computation of the sample's cached histogram slots (n
+// 16-bit entries at `bins`) for `binning` on `stream`.
+hipError_t enqueue_bin_slots(const osc_sample* sample, const osc_binning* binning,
+                             uint16_t* bins, hipStream_t stream);
 
 }  // namespace host
 }  // namespace osc

@@ -33,8 +33,8 @@ void tile_kernel(
     SetConsts sc, SinCosTable sctab, PathConsts pc, BinConsts bc, int64_t n, int64_t ntiles,
     const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
     const double* __restrict__ weight, const double* __restrict__ e_reco,
-    const double* __restrict__ value, double* __restrict__ p_out,
-    double* __restrict__ partial)
+    const uint16_t* __restrict__ bins, const double* __restrict__ value,
+    double* __restrict__ p_out, double* __restrict__ partial)
 {
     extern __shared__ double hist[];
     __shared__ TileTables tabs;
@@ -51,15 +51,13 @@ void tile_kernel(
     __syncthreads();
 
     const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL};
-    const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, value, p_out);
+    const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, bins, value, p_out);
     if (t.n == kTileEvents)
-        tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
-                                                            t.flags, t.weight, t.e_reco,
-                                                            t.value, t.p_out);
+        tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                  t.weight, t.e_reco, t.bins, t.value, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true,
-                                                             t.flags, t.weight, t.e_reco,
-                                                             t.value, t.p_out);
+        tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                   t.weight, t.e_reco, t.bins, t.value, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -88,13 +86,14 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
     __syncthreads();
 
     const LayeredProb prob{&sc, &tabs, &lp};
-    const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, p_out);
+    const TileArrays t =
+        tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, nullptr, p_out);
     if (t.n == kTileEvents)
         tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
-                                                  t.weight, t.e_reco, nullptr, t.p_out);
+                                                  t.weight, t.e_reco, nullptr, nullptr, t.p_out);
     else
         tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
-                                                   t.weight, t.e_reco, nullptr, t.p_out);
+                                                   t.weight, t.e_reco, nullptr, nullptr, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
@@ -133,6 +132,20 @@ __global__ __launch_bounds__(64) void poisson_nll_kernel(const double* __restric
     }
     acc = wave_tree(acc);
     if (lane == 0) out[k] = 2.0 * acc;
+}
+
+// The cached histogram slot of every event of a sample: the LDS slot
+// (hslot) its contribution goes to in the per-event kernels, from the bin
+// of e_reco by the exact rule (a correctly rounded division) and the
+// accumulator of its lane, event index mod kHistLanes (tiles start at
+// multiples of kTileEvents, so an event's lane is its index mod 64).
+__global__ __launch_bounds__(256) void bin_slot_kernel(int64_t n, const double* __restrict__ e_reco,
+                                                       BinConsts bc, uint16_t* __restrict__ out)
+{
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = uint16_t(hslot(lds_bin(bin_floor_exact(e_reco[i], bc), bc),
+                                int(i & (kHistLanes - 1))));
 }
 
 // One-time domain check of a sample: counts of events whose true energy
@@ -175,6 +188,16 @@ hipError_t launch_validate_sample(int64_t n, const double* e_true, const uint8_t
     return hipGetLastError();
 }
 
+hipError_t launch_bin_slots(int64_t n, const double* e_reco, const BinConsts& bc, uint16_t* out,
+                            hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(bin_slot_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, n, e_reco,
+                       bc, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
                               const double* data, int64_t n_data, int nbins, double* out,
                               hipStream_t stream)
@@ -188,8 +211,8 @@ hipError_t launch_poisson_nll(const double* hist, int64_t n_hist, double scale,
 hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const PathConsts& pc, const BinConsts& bc, int64_t n,
                         const double* e_true, const uint8_t* flags, const double* weight,
-                        const double* e_reco, const double* value, double* p_out,
-                        double* partial, hipStream_t stream, hipEvent_t ev_begin,
+                        const double* e_reco, const uint16_t* bins, const double* value,
+                        double* p_out, double* partial, hipStream_t stream, hipEvent_t ev_begin,
                         hipEvent_t ev_end)
 {
     const int64_t ntiles = (n + kTileEvents - 1) / kTileEvents;
@@ -199,8 +222,8 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
     const SinCosTable& sctab = host::sincos_table();
 #define OSC_LAUNCH(M, W, X)                                                                      \
     hipExtLaunchKernelGGL((tile_kernel<M, W, X>), grid, block, lds, stream, ev_begin, ev_end, 0,  \
-                          sc, sctab, pc, bc, n, ntiles, e_true, flags, weight, e_reco, value,     \
-                          p_out, partial)
+                          sc, sctab, pc, bc, n, ntiles, e_true, flags, weight, e_reco, bins,      \
+                          value, p_out, partial)
     if (mode == kReweight) {
         if (mixed) OSC_LAUNCH(kReweight, true, true);
         else OSC_LAUNCH(kReweight, true, false);
@@ -209,6 +232,11 @@ hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
         else if (write_p) OSC_LAUNCH(kPdf, true, false);
         else if (mixed) OSC_LAUNCH(kPdf, false, true);
         else OSC_LAUNCH(kPdf, false, false);
+    } else if (mode == kPdfBinned) {
+        if (write_p && mixed) OSC_LAUNCH(kPdfBinned, true, true);
+        else if (write_p) OSC_LAUNCH(kPdfBinned, true, false);
+        else if (mixed) OSC_LAUNCH(kPdfBinned, false, true);
+        else OSC_LAUNCH(kPdfBinned, false, false);
     } else {
         OSC_LAUNCH(kHist, false, false);
     }
@@ -341,6 +369,10 @@ hipError_t set_kernel_attributes(size_t max_dyn_lds)
         reinterpret_cast<const void*>(&tile_kernel<kPdf, true, true>),
         reinterpret_cast<const void*>(&tile_kernel<kPdf, false, true>),
         reinterpret_cast<const void*>(&tile_kernel<kHist, false, false>),
+        reinterpret_cast<const void*>(&tile_kernel<kPdfBinned, true, false>),
+        reinterpret_cast<const void*>(&tile_kernel<kPdfBinned, false, false>),
+        reinterpret_cast<const void*>(&tile_kernel<kPdfBinned, true, true>),
+        reinterpret_cast<const void*>(&tile_kernel<kPdfBinned, false, true>),
         reinterpret_cast<const void*>(&layered_tile_kernel<kPdf, true>),
         reinterpret_cast<const void*>(&layered_tile_kernel<kPdf, false>),
     };

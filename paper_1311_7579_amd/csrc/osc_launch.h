@@ -6,17 +6,23 @@
 namespace osc {
 
 // mode: 0 = probabilities only, 1 = probabilities + histogram partials,
-// 2 = histogram partials of given values.  partial holds ntiles x
-// (nbins + 2) FP64 entries, tile-major.
+// 2 = histogram partials of given values, 3 = mode 1 with the events'
+// histogram slots read from `bins` (launch_bin_slots) instead of computed
+// from e_reco.  partial holds ntiles x (nbins + 2) FP64 entries, tile-major.
 // mixed selects the FP32-mixed tier (FP64 eigenvalues and phases, FP32
 // sine/cosine and amplitude assembly).  ev_begin / ev_end (optional,
 // created by the caller) receive the kernel's own begin and end times.
 hipError_t launch_tiles(int mode, bool write_p, bool mixed, const SetConsts& sc,
                         const PathConsts& pc, const BinConsts& bc, int64_t n,
                         const double* e_true, const uint8_t* flags, const double* weight,
-                        const double* e_reco, const double* value, double* p_out,
-                        double* partial, hipStream_t stream, hipEvent_t ev_begin = nullptr,
-                        hipEvent_t ev_end = nullptr);
+                        const double* e_reco, const uint16_t* bins, const double* value,
+                        double* p_out, double* partial, hipStream_t stream,
+                        hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+
+// The cached histogram slot of each of n events (reco energies e_reco,
+// binning bc) for mode 3: out holds n 16-bit entries.
+hipError_t launch_bin_slots(int64_t n, const double* e_reco, const BinConsts& bc, uint16_t* out,
+                            hipStream_t stream);
 
 // launch_tiles with P through a layered path (FP64; mode 0 or 1).
 hipError_t launch_layered_tiles(int mode, bool write_p, const SetConsts& sc,

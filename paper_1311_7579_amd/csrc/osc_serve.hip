@@ -117,6 +117,7 @@ struct osc_server {
     osc_ctx* ctx = nullptr;
     int device = 0;
     std::vector<osc_sample> samples;
+    std::vector<uint16_t*> bins;   // per sample: cached histogram slots (device)
     std::vector<size_t> need;   // scratch bytes per sample
     osc_binning binning{};
     int nbt = 0;
@@ -154,9 +155,9 @@ osc_status launch(osc_server* sv, Slot& slot, Request& r)
 {
     const osc::SetConsts sc = osc::host::set_consts(r.params);
     double* scratch = reinterpret_cast<double*>(sv->arena_mem + slot.off);
-    if (osc::host::enqueue_fill(sc, &sv->samples[size_t(r.sample)], &sv->binning,
-                                r.precision == OSC_FP32_MIXED, scratch, slot.d_hist, nullptr,
-                                slot.stream) != hipSuccess)
+    if (osc::host::enqueue_fill(sc, &sv->samples[size_t(r.sample)], sv->bins[size_t(r.sample)],
+                                &sv->binning, r.precision == OSC_FP32_MIXED, scratch,
+                                slot.d_hist, nullptr, slot.stream) != hipSuccess)
         return OSC_ERR_DEVICE;
     r.with_nll = sv->has_data;
     const int nb = sv->binning.nbins;
@@ -256,6 +257,8 @@ void destroy_server(osc_server* sv)
         if (slot.h_hist) (void)hipHostFree(slot.h_hist);
     }
     if (sv->arena_mem) (void)hipFree(sv->arena_mem);
+    for (uint16_t* b : sv->bins)
+        if (b) (void)hipFree(b);
     if (sv->d_data) (void)hipFree(sv->d_data);
     delete sv;
 }
@@ -292,6 +295,17 @@ osc_status osc_server_create(osc_ctx* ctx, const osc_sample* samples, int32_t n_
     sv->slots = std::vector<Slot>(size_t(cfg->slots));
     const size_t budget = size_t(cfg->scratch_budget_bytes) & ~(kArenaAlign - 1);
     bool ok = budget > 0 && hipMalloc(&sv->arena_mem, budget) == hipSuccess;
+    // the reco-energy bins of a resident sample do not change from request
+    // to request: cache each event's histogram slot once
+    sv->bins.assign(sv->samples.size(), nullptr);
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
+    for (size_t k = 0; ok && k < sv->samples.size(); ++k) {
+        const osc_sample& smp = sv->samples[k];
+        if (smp.n == 0) continue;
+        ok = hipMalloc(&sv->bins[k], size_t(smp.n) * sizeof(uint16_t)) == hipSuccess &&
+             osc::host::enqueue_bin_slots(&smp, binning, sv->bins[k], nullptr) == hipSuccess;
+    }
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
     for (Slot& slot : sv->slots) {
         ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess &&
              hipMalloc(&slot.d_hist, size_t(sv->nbt + 1) * sizeof(double)) == hipSuccess &&

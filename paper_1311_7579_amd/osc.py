@@ -119,6 +119,13 @@ def load():
     L.osc_fill_pdf.restype = st
     L.osc_fill_pdf_noalloc.argtypes = L.osc_fill_pdf.argtypes
     L.osc_fill_pdf_noalloc.restype = st
+    L.osc_binned_create.argtypes = [vp, ctypes.POINTER(osc_sample), ctypes.POINTER(osc_binning),
+                                    ctypes.POINTER(vp)]
+    L.osc_binned_create.restype = st
+    L.osc_binned_destroy.argtypes = [vp]
+    L.osc_binned_destroy.restype = st
+    L.osc_fill_pdf_binned.argtypes = [vp, vp, i32, ctypes.c_int, vp, vp, vp]
+    L.osc_fill_pdf_binned.restype = st
     L.osc_fill_hist.argtypes = [vp, i64, vp, vp, vp, ctypes.POINTER(osc_binning), vp, vp]
     L.osc_fill_hist.restype = st
     L.osc_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -336,6 +343,31 @@ class DeviceSample:
         return cls(t(s.e_true), t(s.flags), t(s.weight), t(s.e_reco), s.L_km, s.rho_gcc, s.Ye)
 
 
+class BinnedSample:
+    """An osc_binned: a resident sample with its histogram slots cached for
+    one binning (Context.osc_binned_create)."""
+
+    def __init__(self, handle, ctx, sample, nbins):
+        self.handle, self.ctx, self.sample, self.nbins = handle, ctx, sample, nbins
+
+    def close(self):
+        if self.handle:
+            _check(load().osc_binned_destroy(self.handle), "osc_binned_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Context:
     """An osc_ctx on one device."""
 
@@ -424,6 +456,28 @@ class Context:
                                            ctypes.byref(b), int(precision), hp, pp,
                                            _stream(stream)),
                "osc_fill_pdf_noalloc")
+
+    def osc_binned_create(self, sample: DeviceSample, nbins, lo, hi, e_scale=0.0):
+        """Cache the histogram slot of every event of `sample` for this
+        binning (2 bytes per event); returns a BinnedSample that keeps the
+        sample alive."""
+        cs = self._sample(sample, True)
+        b = osc_binning(int(nbins), float(lo), float(hi), float(e_scale))
+        h = ctypes.c_void_p()
+        _check(load().osc_binned_create(self.handle, ctypes.byref(cs), ctypes.byref(b),
+                                        ctypes.byref(h)), "osc_binned_create")
+        return BinnedSample(h, self, sample, int(nbins))
+
+    def osc_fill_pdf_binned(self, binned, set_index, hist_out, p_out=None, precision=OSC_FP64,
+                            stream=None):
+        if not isinstance(binned, BinnedSample) or binned.ctx is not self or not binned.handle:
+            raise ValueError("binned must be a live BinnedSample of this context")
+        hp, pp = device_vecs(self._hist(hist_out, binned.nbins),
+                             (p_out, "p_out", "float64", dict(n=binned.sample.n, optional=True)),
+                             device=self.device)
+        _check(load().osc_fill_pdf_binned(self.handle, binned.handle, int(set_index),
+                                          int(precision), hp, pp, _stream(stream)),
+               "osc_fill_pdf_binned")
 
     def osc_validate_sample(self, sample: DeviceSample, stream=None):
         """(events with a true energy that is not finite and > 0, events with
