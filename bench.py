@@ -4,7 +4,10 @@ Workload: 1e7 synthetic Monte Carlo events (true E log-uniform on
 [0.1, 10] GeV, nu_mu -> nu_mu / nu_mu -> nu_e at 50 % each, 20 %
 antineutrinos, weights U(0.5, 1.5), reco E = true E x N(1, 0.1)), Table 1
 parameters, 295 km at 2.6 g/cm^3, 50 reco-E bins on [0, 3] GeV, per-event
-P written out.  One step = one osc_fill_pdf call on the resident sample.
+P written out.  The sample is uploaded once and its reco-energy bins are
+cached once (osc_binned_create, 2 bytes per event), outside the timed
+region, as a fitter keeps its Monte Carlo resident.  One step = one
+osc_fill_pdf_binned call: P of every event, w * P, the histogram.
 
 Prints one JSON line: evals/s over the timed steps, p50/p99 latency of
 single calls measured on the host (launch to histogram on the host), the
@@ -26,10 +29,13 @@ N_EVENTS = 10_000_000
 SEED = 1
 NBINS, LO, HI = 50, 0.0, 3.0
 
-# Algorithmic HBM bytes per event of the fused kernel: read E (8), flags (1),
-# weight (8), reco E (8); write P (8).  Histogram partials add
-# (nbins + 2) * 8 B per 1024-event tile (0.4 B/event) and are left out.
-BYTES_PER_EVENT = 33
+# Algorithmic HBM bytes per event of the fused kernel on a binned sample:
+# read E (8), flags (1), weight (8), the cached histogram slot (2); write P
+# (8).  Histogram partials add (nbins + 2) * 8 B per 1024-event tile
+# (0.4 B/event) and are left out.  With bins computed per call the slot is
+# replaced by the 8-byte reco energy (33 B).
+BYTES_PER_EVENT = 27
+BYTES_PER_EVENT_COMPUTED_BINS = 33
 HBM_PEAK_GBS = 8000.0
 SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # Algorithmic FP64 flops per event of the formulation the kernel follows
@@ -37,47 +43,69 @@ SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # inputs 9, cubic coefficients 12, trigonometric seeds (scaling in FP64) 6,
 # one Halley and one Newton step on two roots 72, third root 2,
 # differences, 1/(E Q) and the phase scale 16, coefficients of the
-# projectors X1 and X2 6, two sin and cos - 1 of the phase differences 54
+# projectors X1 and X2 6, two sin and cos - 1 of the phase differences 52
 # (the phase products sit inside their reduction FMAs), numerators of X1
-# and X2 16, amplitude sum 15, |S|^2 3, bin and weighted add 6.
-FLOPS_PER_EVENT = 217
+# and X2 16, amplitude sum 15, |S|^2 3, weighted add 2 (w * P and the add
+# into the histogram).  Computing the bin per call adds 4 (scale, offset,
+# quotient, floor).
+FLOPS_PER_EVENT = 211
+FLOPS_PER_EVENT_COMPUTED_BINS = 215
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
-# HBM traffic of one launch of the fused kernel on this workload, read with
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch) and scaled by
-# what the same counters read for a plain device copy of known size.  Valid
-# only for the kernel sources and build flags it was taken on (sha256 over
-# KERNEL_SOURCES); reported as null once they change.
+# HBM traffic and VALU instruction mix of one launch of the fused kernel on
+# this workload (binned sample, FP64, P written), read with rocprofv3 --pmc
+# (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, scaled by what the same
+# counters read for a plain device copy of known size; SQ_INSTS_VALU and its
+# class counters, wave instructions x 64 / events).  Valid only for the
+# kernel sources and build flags they were taken on (sha256 over
+# KERNEL_SOURCES); reported as null once those change.
 KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_internal.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 122169.5, "fetch_scale": 2.0,    # copy of 512 MiB: FETCH_SIZE 262158 KiB
-    "write_kib": 82825.0, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
-    # SQ_INSTS_VALU per event (wave instructions x 64 / events) and the
-    # quarter-rate transcendentals among them, from the same run
-    "valu_per_event": 195.9, "trans_per_event": 8,
-    "source_sha256": "62f73101d553860446d2ddcf66c4a199e9aab1c6e8ffb584b9afc572c46906d8",
+    "fetch_kib": 92830.6, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 82505.4, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "valu_per_event": 176.8,
+    "classes_per_event": {"fp64": 130.5, "fp64_trans": 3.0, "fp32": 12.0, "fp32_trans": 4.0,
+                          "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 15.25},
+    "source_sha256": "0d6be9d56f092f30254538196819a4e51a931ca6a732071859da53ff39d4e8dc",
 }
-# VALU issue: one wave instruction per SIMD every 4 cycles (a quarter-rate
-# transcendental takes 16), 1024 SIMDs at the 2.4 GHz peak engine clock.
+# Issue time of one wave instruction on one SIMD, measured on the box with
+# probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32
+# 1.06, v_rcp_f64 6.75, v_cos_f32 3.38 and v_sqrt_f32 about 4 (3.7 for the
+# FP32 transcendentals, two cos and a sqrt and an rsq per event).
+# Conversions and 64-bit integer operations are taken at the FP64 rate and
+# the unclassified remainder (moves, selects) at the FP32 rate: assumed,
+# not measured.  2.08 ns for a 4-cycle FP64 instruction is an engine clock
+# of 1.92 GHz under this load, against the 2.4 GHz of the published peak.
+ISSUE_NS = {"fp64": 2.08, "fp64_trans": 6.75, "fp32": 1.06, "fp32_trans": 3.7,
+            "cvt": 2.08, "int32": 1.06, "int64": 2.08, "other": 1.06}
 VALU_SIMDS = 1024
 CLOCK_HZ = 2.4e9
 
 
-def valu_issue(kernel_ms):
-    """Fraction of the kernel's duration the SIMDs need just to issue its
-    VALU instructions (counter figures of the current sources, else None)."""
+def valu_issue(kernel_ms, flops_per_event):
+    """Where the FP64 roofline fraction goes, from the counter mix of the
+    current sources (None once they change): the fraction equals
+    clock x mix x issue, with clock = the engine clock the measured issue
+    rates imply over 2.4 GHz, mix = the time the event's flops would need
+    as FP64 FMAs over the time its instruction mix needs, and issue = that
+    instruction time over the kernel's duration."""
     if kernel_sources_sha256() != COUNTER_TRAFFIC["source_sha256"]:
         return None
-    per_event = COUNTER_TRAFFIC["valu_per_event"]
-    trans = COUNTER_TRAFFIC["trans_per_event"]
-    cycles = (per_event * 4 + trans * 12) * (N_EVENTS / 64) / VALU_SIMDS
-    need_ms = cycles / CLOCK_HZ * 1e3
-    return {"valu_insts_per_event": per_event, "transcendentals_per_event": trans,
-            "issue_ms_at_peak_clock": need_ms, "frac": need_ms / kernel_ms}
+    cls = COUNTER_TRAFFIC["classes_per_event"]
+    ns = sum(cls[k] * ISSUE_NS[k] for k in cls)            # per wave-event, one SIMD
+    wave_events = N_EVENTS / 64 / VALU_SIMDS
+    issue_ms = ns * wave_events * 1e-6
+    clock = (4 / (ISSUE_NS["fp64"] * 1e-9)) / CLOCK_HZ
+    mix = (flops_per_event / 2 * ISSUE_NS["fp64"]) / ns
+    return {"valu_insts_per_event": COUNTER_TRAFFIC["valu_per_event"],
+            "classes_per_event": cls, "issue_ns_per_wave_event": ns,
+            "issue_ms_at_measured_rates": issue_ms, "frac": issue_ms / kernel_ms,
+            "decomposition": {"clock": clock, "mix": mix, "issue": issue_ms / kernel_ms,
+                              "product": clock * mix * issue_ms / kernel_ms}}
 
 
 def parse():
@@ -88,10 +116,8 @@ def parse():
     ap.add_argument("--latency-calls", type=int, default=1000)
     ap.add_argument("--cpu-events", type=int, default=10_000_000,
                     help="events of the oracle's timed slice (all host threads)")
-    ap.add_argument("--cpu-events-1t", type=int, default=2_000_000,
+    ap.add_argument("--cpu-events-1t", type=int, default=1_000_000,
                     help="events of the oracle's single-thread slice")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum wall time of the oracle's all-thread passes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form measurement (64 parameter sets, both tiers)")
@@ -104,6 +130,17 @@ def parse():
                     help="skip the bin-centre measurement (template + binning effect)")
     ap.add_argument("--no-layered", action="store_true",
                     help="skip the layered-matter measurement (5-layer Earth path)")
+    ap.add_argument("--tier", choices=("fp64", "mixed"), default=None,
+                    help="precision tier of the timed step (profiling runs; the benchmark "
+                         "line is FP64) or of --batch-schedule (FP32-mixed by default)")
+    ap.add_argument("--computed-bins", action="store_true",
+                    help="time osc_fill_pdf (bins computed per call) as the step")
+    ap.add_argument("--batch-schedule", type=int, choices=(0, 1, 2), default=None,
+                    help="only run the 256-set x 4-sample batched form with this schedule "
+                         "(0 dynamic queue, 1 static stride, 2 one workgroup per tile), "
+                         "--sets-per-item sets per work item, --steps launches; for "
+                         "per-schedule profiles")
+    ap.add_argument("--sets-per-item", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run torch device-to-device copies of MIB MiB (HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -142,41 +179,96 @@ def counter_traffic():
     return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
 
 
-def cpu_baseline(sample, n_all, n_one, min_seconds):
-    """The oracle (P per event, contract histogram) on the host: whole passes
-    over the first n_all events with every OpenMP thread until min_seconds
-    have passed, then one single-thread pass over the first n_one."""
+def host_cores():
+    """Physical cores of the host (distinct (socket, core) pairs of
+    /proc/cpuinfo), and the logical CPUs this process may run on."""
+    pairs, phys = set(), None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    pairs.add((phys, val))
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return (len(pairs) or None), allowed
+
+
+def cpu_baseline(sample, n_all, n_one, reps=5):
+    """The oracle (P per event and the contract histogram, fill_pdf with P
+    written) timed on the host: the unchanged source built at -O3
+    -march=native for this host, the median of `reps` passes over the first
+    n_all events with every OpenMP thread and over the first n_one events
+    with one thread.  The portable -O2 build the tests use is timed the
+    same way and reported beside it."""
+    import numpy as np
     import oracle
     from paper_1311_7579_amd import workload
 
-    def run(n):
-        t0 = time.perf_counter()
-        oracle.fill_pdf(workload.TABLE1, sample.L_km, sample.rho_gcc, sample.Ye,
-                        sample.e_true[:n], sample.flags[:n], sample.weight[:n],
-                        sample.e_reco[:n], NBINS, LO, HI, want_p=True)
-        return time.perf_counter() - t0
+    def rate(n):
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            oracle.fill_pdf(workload.TABLE1, sample.L_km, sample.rho_gcc, sample.Ye,
+                            sample.e_true[:n], sample.flags[:n], sample.weight[:n],
+                            sample.e_reco[:n], NBINS, LO, HI, want_p=True)
+            times.append(time.perf_counter() - t0)
+        return n / float(np.median(times)), float(np.sum(times))
 
-    threads = oracle.num_threads()
-    t_all, passes = 0.0, 0
-    while passes == 0 or t_all < min_seconds:
-        t_all += run(n_all)
-        passes += 1
-    oracle.set_num_threads(1)
-    t_one = run(n_one)
-    oracle.set_num_threads(threads)
+    def both():
+        threads = oracle.num_threads()
+        all_rate, all_s = rate(n_all)
+        oracle.set_num_threads(1)
+        one_rate, one_s = rate(n_one)
+        oracle.set_num_threads(threads)
+        return threads, all_rate, all_s, one_rate, one_s
+
+    portable = both()
+    oracle.use_native_build()
+    threads, all_rate, all_s, one_rate, one_s = both()
+    physical, allowed = host_cores()
     return {
-        "value": passes * n_all / t_all, "unit": "evals/s", "cores": threads, "kind": "oracle",
-        "sample": f"{passes} passes over the first {n_all} events of the 1e7-event workload "
-                  f"(fill_pdf with P written), {threads} OpenMP threads, {t_all:.1f} s wall",
-        "single_core_value": n_one / t_one,
-        "single_core_sample": f"first {n_one} events, 1 thread ({t_one:.2f} s)",
+        "value": all_rate, "unit": "evals/s", "cores": threads, "kind": "oracle",
+        "sample": f"median of {reps} passes over the first {n_all} events of the 1e7-event "
+                  f"workload (fill_pdf with P written), {threads} OpenMP threads; oracle source "
+                  f"built with gcc -O3 -march=native -ffp-contract=off on this host "
+                  f"({all_s:.1f} s in all)",
+        "single_core_value": one_rate,
+        "single_core_sample": f"median of {reps} passes over the first {n_one} events, "
+                              f"1 thread ({one_s:.1f} s in all)",
+        "threads_used": threads, "host_physical_cores": physical,
+        "logical_cpus_available": allowed,
+        "portable_O2_build": {"value": portable[1], "single_core_value": portable[3]},
     }
 
 
-def precision_form(osc, ctx, ds, n_sets=64, set_seed=3):
-    """The 1e7 events under 64 parameter sets, once per tier: throughput of
-    each tier and the largest |P_mixed - P_fp64| over all events and sets."""
+# The paper's own timing comparison (Sec. 2.2 and its hardware statement):
+# context for the speed-ups this benchmark measures, not a target.
+PAPER_CONTEXT = {
+    "gpu_speedup_vs_one_cpu_core": 132,
+    "at_calculations": 1.45e6,
+    "gpu": "NVIDIA Tesla M2070 (448 CUDA cores at 1.15 GHz), CUDA 5, FP64",
+    "cpu": "Intel Xeon E5640 (4 cores at 2.67 GHz), one core, gcc 4.6.3 -O2, FP64",
+    "openmp_speedup_vs_one_core": "2-3x with 4 threads",
+    "headline": "about two orders of magnitude over a single CPU core",
+}
+
+
+def precision_form(osc, ctx, ds, binned, n_sets=64, set_seed=3, n_oracle=100_000):
+    """The 1e7 events under 64 parameter sets, once per tier (binned
+    sample, P written): throughput of each tier, and for every set the
+    largest |P_mixed - P_fp64| over all events (on the device) and the
+    largest |P - P_oracle| of each tier over the first n_oracle events."""
+    import numpy as np
     import torch
+    import oracle
     from paper_1311_7579_amd import workload
     sets = workload.make_param_sets(n_sets, set_seed)
     ctx.osc_set_params(sets)
@@ -187,25 +279,40 @@ def precision_form(osc, ctx, ds, n_sets=64, set_seed=3):
     out = {}
     for name, prec, buf in (("fp64", osc.OSC_FP64, p64), ("fp32_mixed", osc.OSC_FP32_MIXED, pmx)):
         for k in range(2):   # warm-up
-            ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, buf, precision=prec)
+            ctx.osc_fill_pdf_binned(binned, k, h, buf, precision=prec)
         torch.cuda.synchronize()
         ctx.osc_profile_enable(True)
         t0 = time.perf_counter()
         for k in range(n_sets):
-            ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, buf, precision=prec)
+            ctx.osc_fill_pdf_binned(binned, k, h, buf, precision=prec)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ev_ms, ev_n, merge_ms, merge_n = ctx.osc_profile_read()
         ctx.osc_profile_enable(False)
         out[name] = {"evals_per_s": n * n_sets / dt, "kernel_ms": ev_ms / max(ev_n, 1),
                      "merge_ms": merge_ms / max(merge_n, 1)}
-    worst = 0.0
+    e = ds.e_true[:n_oracle].cpu().numpy()
+    f = ds.flags[:n_oracle].cpu().numpy()
+    rows = []
     for k in range(n_sets):
-        ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, p64, precision=osc.OSC_FP64)
-        ctx.osc_fill_pdf(ds, k, NBINS, LO, HI, h, pmx, precision=osc.OSC_FP32_MIXED)
-        worst = max(worst, float((pmx - p64).abs().max()))
-    out["max_abs_dP_mixed_vs_fp64"] = worst
-    out["config"] = f"{n} events x {n_sets} parameter sets (seed {set_seed}), P written"
+        ctx.osc_fill_pdf_binned(binned, k, h, p64, precision=osc.OSC_FP64)
+        ctx.osc_fill_pdf_binned(binned, k, h, pmx, precision=osc.OSC_FP32_MIXED)
+        d_all = float((pmx - p64).abs().max())
+        po = oracle.prob_batch(sets[k], ds.L_km, ds.rho_gcc, ds.Ye, e, f)
+        d_mx = float(np.abs(pmx[:n_oracle].cpu().numpy() - po).max())
+        d_64 = float(np.abs(p64[:n_oracle].cpu().numpy() - po).max())
+        rows.append([k, d_all, d_mx, d_64])
+    arr = np.array(rows)
+    out["per_set_error"] = {
+        "columns": ["set", "max_abs_dP_mixed_vs_fp64_all_events",
+                    f"max_abs_dP_mixed_vs_oracle_first_{n_oracle}",
+                    f"max_abs_dP_fp64_vs_oracle_first_{n_oracle}"],
+        "rows": rows}
+    out["max_abs_dP_mixed_vs_fp64"] = float(arr[:, 1].max())
+    out["max_abs_dP_mixed_vs_oracle"] = float(arr[:, 2].max())
+    out["max_abs_dP_fp64_vs_oracle"] = float(arr[:, 3].max())
+    out["config"] = (f"{n} events x {n_sets} parameter sets (seed {set_seed}), P written, "
+                     f"bins cached; oracle on the first {n_oracle} events of every set")
     ctx.osc_set_params([workload.TABLE1])
     return out
 
@@ -340,6 +447,37 @@ def batched_form(osc, ctx, reps=5):
     return out
 
 
+def batch_schedule_run(osc, ctx, args):
+    """The batched form (256 sets x 4 samples, FP32-mixed unless --tier
+    fp64) in one fixed configuration, launched --steps times after --warmup
+    launches: for kernel traces and counters per schedule."""
+    import torch
+    from paper_1311_7579_amd import workload
+    samples = workload.make_batched_samples()
+    ds = [osc.DeviceSample.from_host(s) for s in samples]
+    sets = workload.make_param_sets(256, 4)
+    prec = osc.OSC_FP64 if args.tier == "fp64" else osc.OSC_FP32_MIXED
+    batch = osc.Batch(ctx, ds, NBINS, LO, HI, precision=prec, max_sets=256)
+    try:
+        batch.config = dict(sets_per_item=args.sets_per_item, schedule=args.batch_schedule,
+                            waves_per_cu=0, use_graph=1)
+        hist = torch.empty((256, 4, NBINS + 2), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            batch.run(sets, hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.run(sets, hist)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    finally:
+        batch.close()
+    evals = sum(s.n for s in samples) * len(sets)
+    return {"batch_schedule": args.batch_schedule, "sets_per_item": args.sets_per_item,
+            "tier": "fp64" if prec == osc.OSC_FP64 else "fp32_mixed",
+            "ms_per_launch": dt * 1e3, "evals_per_s": evals / dt}
+
+
 SERVE_BUDGET = 24 << 20    # device scratch shared by requests in flight
 
 
@@ -441,12 +579,23 @@ def main():
     ctx = osc.Context(0)
     ctx.osc_set_params([workload.TABLE1])
     ds = osc.DeviceSample.from_host(s)
+    binned = ctx.osc_binned_create(ds, NBINS, LO, HI)
     hist = torch.empty(NBINS + 2, dtype=torch.float64, device="cuda")
     p_out = torch.empty(N_EVENTS, dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
+    tier = osc.OSC_FP32_MIXED if args.tier == "mixed" else osc.OSC_FP64
 
-    def step():
-        ctx.osc_fill_pdf(ds, 0, NBINS, LO, HI, hist, p_out, stream=stream)
+    if args.batch_schedule is not None:
+        print(json.dumps(batch_schedule_run(osc, ctx, args)), flush=True)
+        return
+
+    def step_binned():
+        ctx.osc_fill_pdf_binned(binned, 0, hist, p_out, precision=tier, stream=stream)
+
+    def step_computed():
+        ctx.osc_fill_pdf(ds, 0, NBINS, LO, HI, hist, p_out, precision=tier, stream=stream)
+
+    step = step_computed if args.computed_bins else step_binned
 
     # The GPU's clocks take tens of milliseconds of load to settle: untimed
     # steps for at least SETTLE_S seconds, then the W warm-up steps, then the
@@ -489,25 +638,44 @@ def main():
     kernel_ms = ev_ms / max(ev_n, 1)
     waves_per_cu = ctx.osc_occupancy(NBINS, True)
     merge_avg_ms = merge_ms / max(merge_n, 1)
+    # the same step with the bin of every event computed per call
+    other = step_binned if args.computed_bins else step_computed
+    for _ in range(args.warmup):
+        other()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        other()
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    ctx.osc_profile_enable(True)
+    for _ in range(max(args.steps, 50)):
+        other()
+    o_ms, o_n, _, _ = ctx.osc_profile_read()
+    ctx.osc_profile_enable(False)
+    flops_ev = FLOPS_PER_EVENT_COMPUTED_BINS if args.computed_bins else FLOPS_PER_EVENT
+    bytes_ev = BYTES_PER_EVENT_COMPUTED_BINS if args.computed_bins else BYTES_PER_EVENT
 
     # The fused kernel is bound by VALU issue (FP64 arithmetic), not by HBM:
     # roofline against the FP64 vector peak, HBM position alongside.
-    achieved_gbs = BYTES_PER_EVENT * N_EVENTS / (kernel_ms * 1e-3) / 1e9
-    fp64_tflops = FLOPS_PER_EVENT * N_EVENTS / (kernel_ms * 1e-3) / 1e12
-    traffic = counter_traffic()
+    achieved_gbs = bytes_ev * N_EVENTS / (kernel_ms * 1e-3) / 1e9
+    fp64_tflops = flops_ev * N_EVENTS / (kernel_ms * 1e-3) / 1e12
+    plain = not args.computed_bins and tier == osc.OSC_FP64
+    traffic = counter_traffic() if plain else None
+    mode = "kPdf" if args.computed_bins else "kPdfBinned"
     roofline = {
         "bound": "alu", "achieved": fp64_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": fp64_tflops / FP64_PEAK_TFLOPS, "traffic": traffic,
-        "kernel": "tile_kernel<kPdf, write P, FP64>", "kernel_ms": kernel_ms,
-        "flops_per_event": FLOPS_PER_EVENT, "events_per_launch": N_EVENTS,
+        "kernel": f"tile_kernel<{mode}, write P, {'FP32-mixed' if tier else 'FP64'}>",
+        "kernel_ms": kernel_ms, "flops_per_event": flops_ev, "events_per_launch": N_EVENTS,
         "hbm": {"achieved_GBs": achieved_gbs, "peak_GBs": HBM_PEAK_GBS,
                 "frac": achieved_gbs / HBM_PEAK_GBS,
-                "algorithmic_bytes_per_event": BYTES_PER_EVENT,
-                "traffic_over_algorithmic": (traffic / (BYTES_PER_EVENT * N_EVENTS)
+                "algorithmic_bytes_per_event": bytes_ev,
+                "traffic_over_algorithmic": (traffic / (bytes_ev * N_EVENTS)
                                              if traffic else None)},
         "merge_kernel_ms": merge_avg_ms,
         "resident_waves_per_cu": waves_per_cu,
-        "valu_issue": valu_issue(kernel_ms),
+        "valu_issue": valu_issue(kernel_ms, flops_ev) if plain else None,
     }
 
     result = {
@@ -517,15 +685,24 @@ def main():
         "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "plain FP64 reweight + 50-bin reco-E PDF, 1e7 events x 1 parameter "
-                               "set (Table 1, 295 km, 2.6 g/cm^3), per-event P written",
+                               "set (Table 1, 295 km, 2.6 g/cm^3), per-event P written, reco-E "
+                               "bins cached at upload",
                    "events": N_EVENTS, "param_sets": 1, "nbins": NBINS, "range_GeV": [LO, HI],
-                   "seed": SEED, "parallelism": "single GPU"},
+                   "seed": SEED, "parallelism": "single GPU",
+                   "tier": "fp32_mixed" if tier else "fp64",
+                   "bins": "computed per call" if args.computed_bins else "cached"},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "calls": args.latency_calls},
         "roofline": roofline,
+        ("cached_bins" if args.computed_bins else "computed_bins"): {
+            "ms_per_step": other_ms, "kernel_ms": o_ms / max(o_n, 1),
+            "evals_per_s": N_EVENTS / (other_ms * 1e-3),
+            "note": "the same step through " + ("osc_fill_pdf_binned" if args.computed_bins
+                                                else "osc_fill_pdf (bin of every event "
+                                                     "computed per call)")},
     }
     if not args.no_forms:
-        result["precision_form"] = precision_form(osc, ctx, ds)
+        result["precision_form"] = precision_form(osc, ctx, ds, binned)
     if not args.no_batch:
         result["batched_form"] = batched_form(osc, ctx)
     if not args.no_bincentre:
@@ -535,10 +712,20 @@ def main():
     if not args.no_serve:
         result["serving_form"] = serving_form(osc, ctx, args.serve_requests)
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(s, args.cpu_events, args.cpu_events_1t,
-                                              args.cpu_seconds)
-        result["speedup_vs_cpu_all_cores"] = value / result["cpu_baseline"]["value"]
-        result["speedup_vs_cpu_one_core"] = value / result["cpu_baseline"]["single_core_value"]
+        result["cpu_baseline"] = cpu_baseline(s, args.cpu_events, args.cpu_events_1t)
+        cb = result["cpu_baseline"]
+        result["speedup_vs_cpu_all_cores"] = value / cb["value"]
+        result["speedup_vs_cpu_one_core"] = value / cb["single_core_value"]
+        result["paper_context"] = dict(
+            PAPER_CONTEXT,
+            this_run={"gpu_speedup_vs_one_cpu_core": value / cb["single_core_value"],
+                      "gpu_speedup_vs_all_threads": value / cb["value"],
+                      "openmp_speedup_vs_one_core": cb["value"] / cb["single_core_value"],
+                      "openmp_threads": cb["threads_used"],
+                      "gpu": "one AMD Instinct MI355X (gfx950)",
+                      "cpu": f"{cb['threads_used']} OpenMP threads on a host with "
+                             f"{cb['host_physical_cores']} physical cores"})
+    binned.close()
     ctx.close()
     print(json.dumps(result), flush=True)
 

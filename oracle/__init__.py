@@ -15,6 +15,7 @@ import os
 import numpy as np
 
 from .build import LIB as _LIB_PATH
+from .build import NATIVE_LIB as _NATIVE_LIB_PATH
 
 _FIELDS = ("sin2_th12", "sin2_th23", "sin2_th13", "dm2_32", "dm2_21", "delta_cp")
 
@@ -43,6 +44,17 @@ def to_params(p) -> OracleParams:
 
 
 _lib = None
+
+
+def use_native_build() -> str:
+    """Switch this process to the -O3 -march=native build of the same
+    source (building it for this host first): CPU timing only; the tests
+    use the portable build."""
+    global _lib, _LIB_PATH
+    from .build import build
+    build(native=True)
+    _LIB_PATH, _lib = _NATIVE_LIB_PATH, None
+    return _LIB_PATH
 
 
 def lib():

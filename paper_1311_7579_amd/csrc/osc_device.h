@@ -24,8 +24,8 @@ static_assert(kLaneEvents % kGroup == 0, "the group size divides the events per 
 // comes out of one FMA against 1.5 * 2^52 (n lands in the low mantissa
 // bits), u = a b - n (|u| <= 1/2) out of a second one, so the reduction is
 // exact up to the final rounding of u.  With r = u pi/32 (|r| <= pi/64):
-//   sin r      = r + r^3 (P3 + P5 u^2 + P7 u^4)   (Taylor, scaled to u;
-//                truncation below 7e-18),
+//   sin r      = u (pi/32 + u^2 (P3 + P5 u^2 + P7 u^4))   (Taylor, scaled
+//                to u; truncation below 7e-18),
 //   cos r - 1  = u^2 (Q2 + Q4 u^2 + Q6 u^4)        (least-maximum absolute
 //                error fit on |u| <= 1/2, error below 8e-18),
 // and the angle-addition formulas with the anchor k = n mod 64 from LDS:
@@ -54,7 +54,7 @@ __device__ __forceinline__ void phase_sincos(double a, double b, const SinCosL* 
     const double u = __builtin_fma(a, b, -n);
     const SinCosL k = table[__double2loint(t) & 63];
     const double z = u * u;
-    const double s = __builtin_fma(u * z, __builtin_fma(z, __builtin_fma(z, kP7, kP5), kP3), u * kStep);
+    const double s = u * __builtin_fma(z, __builtin_fma(z, __builtin_fma(z, kP7, kP5), kP3), kStep);
     const double cm = z * __builtin_fma(z, __builtin_fma(z, kQ6, kQ4), kQ2);
     sn = __builtin_fma(k.s, cm, __builtin_fma(k.c, s, k.s));
     cm1 = __builtin_fma(k.c, cm, __builtin_fma(-k.s, s, k.cm1));

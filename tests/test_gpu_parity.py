@@ -20,7 +20,8 @@ import pytest
 
 import oracle
 from paper_1311_7579_amd import workload
-from helpers import P_TOL, MIXED_TOL, assert_bits_equal, bins_np, hist_tolerance
+from helpers import (MIXED_TOL, MIXED_TOL_BROAD, MIXED_TOL_C3, P_TOL, assert_bits_equal,
+                     bins_np, hist_tolerance)
 
 pytestmark = pytest.mark.gpu
 
@@ -207,7 +208,7 @@ def test_mixed_tier_matter_term_domain(osc, ctx):
             finally:
                 ctx.osc_set_params([workload.TABLE1])
             want = oracle.prob_batch(p, s.L_km, s.rho_gcc, s.Ye, E, f)
-            tol = MIXED_TOL + 64 * 2.0 ** -24 * large_a_conditioning(p, s, f)
+            tol = MIXED_TOL_BROAD + 64 * 2.0 ** -24 * large_a_conditioning(p, s, f)
             assert np.all(np.abs(got - want) <= tol), (a_max, p, float(np.abs(got - want).max()))
 
 
@@ -414,7 +415,7 @@ def test_fill_pdf_invalid_flags_nan_bins(osc, ctx, precision):
     applied to the kernel's own P, NaN in the same bins as the oracle's
     histogram, and within the tier's tolerance of it elsewhere."""
     prec = osc.OSC_FP64 if precision == "fp64" else osc.OSC_FP32_MIXED
-    tol_p = P_TOL if precision == "fp64" else MIXED_TOL
+    tol_p = P_TOL if precision == "fp64" else MIXED_TOL_C3
     s = workload.make_sample(70_001, 13)
     bad = np.array([5, 1030, 1031, 40_000, 70_000])
     s.flags[bad] = np.array([3, 0xFF, 1 << 5, 3 << 2, 35], dtype=np.uint8)
@@ -465,7 +466,7 @@ def test_fill_pdf_max_nbins(osc, ctx, precision):
     ctx.osc_fill_pdf(ds, 0, nb, 0.0, 10.0, h, p, precision=prec)
     P = host(p)
     want = oracle.prob_batch(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags)
-    assert np.abs(P - want).max() <= (P_TOL if precision == "fp64" else MIXED_TOL)
+    assert np.abs(P - want).max() <= (P_TOL if precision == "fp64" else MIXED_TOL_C3)
     bins = oracle.bin_indices(s.e_reco, 0.0, 10.0, nb)
     np.testing.assert_array_equal(host(h), oracle.hist_contract(s.weight * P, bins, nb + 2))
 
@@ -560,12 +561,14 @@ def test_invalid_arguments_raise(osc, ctx):
 
 # --------------------------------------------------------------- FP32-mixed tier
 # FP64 eigenvalues and phase differences, FP32 sine/cosine and amplitude
-# assembly; the tier's tolerance MIXED_TOL is derived in helpers.py.
+# assembly; the tier's tolerances (MIXED_TOL_C3 for the C3 draw at 295 km,
+# MIXED_TOL for those sets at any baseline, MIXED_TOL_BROAD for arbitrary
+# angles) and their derivation are in helpers.py.
 
 
 def test_mixed_tier_c3_parameter_sets(osc, ctx):
     """1e7 events x 64 parameter sets (C3 draw): mixed-tier P within
-    MIXED_TOL of the FP64 tier on every event and of the oracle on a 1e5
+    MIXED_TOL_C3 of the FP64 tier on every event and of the oracle on a 1e5
     subsample; histograms within the carried bound; the reduction of the
     mixed tier's own P is bit-exact."""
     sets = workload.make_param_sets(64, 3)
@@ -590,15 +593,15 @@ def test_mixed_tier_c3_parameter_sets(osc, ctx):
             hm = host(hmx)
             bins = bins_np(s.e_reco, 0.0, 3.0, 50)
             sw = np.bincount(bins, weights=s.weight, minlength=52)
-            assert (np.abs(hm - host(h64)) <= MIXED_TOL * sw + 1e-9).all()
+            assert (np.abs(hm - host(h64)) <= MIXED_TOL_C3 * sw + 1e-9).all()
             if k % 16 == 0:
                 hh = torch.empty(52, dtype=torch.float64, device="cuda")
                 ctx.osc_fill_hist(pmx, ds.weight, ds.e_reco, 50, 0.0, 3.0, hh)
                 np.testing.assert_array_equal(host(hh), hm)
         print(f"mixed tier: max |P_mixed - P_fp64| = {worst_gpu:.3g}, "
               f"max |P_mixed - P_oracle| (1e5 x 64) = {worst_oracle:.3g}")
-        assert worst_gpu <= MIXED_TOL
-        assert worst_oracle <= MIXED_TOL
+        assert worst_gpu <= MIXED_TOL_C3
+        assert worst_oracle <= MIXED_TOL_C3
     finally:
         ctx.osc_set_params([workload.TABLE1])
 
@@ -616,7 +619,8 @@ def test_mixed_tier_all_channels(osc, ctx):
                 pm = torch.empty(s.n, dtype=torch.float64, device="cuda")
                 ctx.osc_fill_pdf(ds, k, 50, 0.0, 3.0, h, pm, precision=osc.OSC_FP32_MIXED)
                 po = oracle.prob_batch(p, L, rho, s.Ye, s.e_true, s.flags)
-                assert np.abs(host(pm) - po).max() <= MIXED_TOL, (L, rho, k)
+                tol = MIXED_TOL if p is workload.TABLE1 else MIXED_TOL_BROAD
+                assert np.abs(host(pm) - po).max() <= tol, (L, rho, k)
     finally:
         ctx.osc_set_params([workload.TABLE1])
 
