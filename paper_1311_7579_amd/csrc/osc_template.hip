@@ -74,18 +74,41 @@ __global__ __launch_bounds__(256) void template_bounds_kernel(int64_t n,
     if (i == n - 1 || keys[i + 1] != k) last[k] = uint32_t(i + 1);
 }
 
-// Weight sum of every cell, its events in ascending event order from +0.0.
+// The weights in sorted order: ws[i] = weight[idx[i]] (independent loads,
+// so the per-cell sums below stream contiguous memory instead of waiting
+// on one dependent gather per addition).
+__global__ __launch_bounds__(256) void template_gather_kernel(int64_t n,
+                                                              const uint32_t* __restrict__ idx,
+                                                              const double* __restrict__ weight,
+                                                              double* __restrict__ ws)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) ws[i] = weight[idx[i]];
+}
+
+// Weight sum of every cell, its events in ascending event order from +0.0:
+// one thread per cell adds its contiguous run of ws one value after the
+// other, with the loads of kSumBatch values issued ahead of their adds.
+constexpr uint32_t kSumBatch = 16;
 __global__ __launch_bounds__(256) void template_sum_kernel(uint32_t n_cells,
                                                            const uint32_t* __restrict__ first,
                                                            const uint32_t* __restrict__ last,
-                                                           const uint32_t* __restrict__ idx,
-                                                           const double* __restrict__ weight,
+                                                           const double* __restrict__ ws,
                                                            double* __restrict__ T)
 {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= n_cells) return;
     double s = 0.0;
-    for (uint32_t i = first[c]; i < last[c]; ++i) s = s + weight[idx[i]];
+    uint32_t i = first[c];
+    const uint32_t end = last[c];
+    for (; end - i >= kSumBatch && i < end; i += kSumBatch) {
+        double v[kSumBatch];
+#pragma unroll
+        for (uint32_t j = 0; j < kSumBatch; ++j) v[j] = ws[i + j];
+#pragma unroll
+        for (uint32_t j = 0; j < kSumBatch; ++j) s = s + v[j];
+    }
+    for (; i < end; ++i) s = s + ws[i];
     T[c] = s;
 }
 
@@ -198,6 +221,7 @@ osc_status osc_template_create(osc_ctx* ctx, const osc_sample* sample,
     hipStream_t s = nullptr;
     uint32_t *keys = nullptr, *idx = nullptr, *skeys = nullptr, *sidx = nullptr;
     uint32_t *first = nullptr, *last = nullptr;
+    double* ws = nullptr;
     void* tmp = nullptr;
     size_t tmp_bytes = 0;
     osc_status st = OSC_OK;
@@ -211,6 +235,7 @@ osc_status osc_template_create(osc_ctx* ctx, const osc_sample* sample,
     if (st == OSC_OK &&
         (hipMalloc(&keys, nb) != hipSuccess || hipMalloc(&idx, nb) != hipSuccess ||
          hipMalloc(&skeys, nb) != hipSuccess || hipMalloc(&sidx, nb) != hipSuccess ||
+         hipMalloc(&ws, size_t(n > 0 ? n : 1) * sizeof(double)) != hipSuccess ||
          hipMalloc(&first, size_t(n_cells) * sizeof(uint32_t)) != hipSuccess ||
          hipMalloc(&last, size_t(n_cells) * sizeof(uint32_t)) != hipSuccess))
         st = OSC_ERR_OUT_OF_MEMORY;
@@ -236,11 +261,15 @@ osc_status osc_template_create(osc_ctx* ctx, const osc_sample* sample,
                                    dim3(256), 0, s, n, skeys, n_cells, first, last);
                 e = hipGetLastError();
             }
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(osc::template_gather_kernel, dim3(blocks_for(n, 256)),
+                                   dim3(256), 0, s, n, sidx, sample->weight, ws);
+                e = hipGetLastError();
+            }
         }
         if (e == hipSuccess) {
             hipLaunchKernelGGL(osc::template_sum_kernel, dim3(blocks_for(n_cells, 256)),
-                               dim3(256), 0, s, n_cells, first, last, sidx, sample->weight,
-                               tp->d_T);
+                               dim3(256), 0, s, n_cells, first, last, ws, tp->d_T);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -268,7 +297,7 @@ osc_status osc_template_create(osc_ctx* ctx, const osc_sample* sample,
     }
     for (void* p : {static_cast<void*>(keys), static_cast<void*>(idx), static_cast<void*>(skeys),
                     static_cast<void*>(sidx), static_cast<void*>(first), static_cast<void*>(last),
-                    tmp})
+                    static_cast<void*>(ws), tmp})
         if (p) (void)hipFree(p);
     if (s) (void)hipStreamDestroy(s);
     if (st != OSC_OK) {
