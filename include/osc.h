@@ -71,7 +71,8 @@ typedef struct {
  *   flags   one byte per event: bits 0-1 alpha, bits 2-3 beta (3 is
  *           invalid), bit 4 antineutrino, bits 5-7 zero.  Invalid flag
  *           bytes give P = NaN;
- *   weight  FP64 Monte Carlo weight (only read by osc_fill_pdf);
+ *   weight  FP64 Monte Carlo weight, any value (only read by the
+ *           histogram calls);
  *   e_reco  FP64 reconstructed energy in GeV (only read by osc_fill_pdf).
  * L_km >= 0, rho_gcc >= 0, 0 <= Ye <= 1 describe the constant-density path. */
 typedef struct {
@@ -155,7 +156,11 @@ osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
  * and receives its additions in ascending m and, within one m, in
  * ascending l; per bin, the A accumulators of a tile meet in the complete
  * binary tree over accumulator index; the tile results meet in the
- * complete binary tree over tile index, padded with +0.0 to a power of two. */
+ * complete binary tree over tile index, padded with +0.0 to a power of two.
+ * Every addition is an IEEE FP64 round-to-nearest-even addition, for any
+ * contribution: negative, +-0, subnormal, infinite and NaN weights (or P)
+ * enter the sum as they are, with the same bits as that order of plain
+ * FP64 additions (a NaN's payload aside). */
 osc_status osc_fill_pdf(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         const osc_binning* binning, osc_precision precision,
                         double* hist_out, double* p_out, void* stream);
