@@ -111,8 +111,8 @@ def valu_issue(kernel_ms, flops_per_event):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-calls", type=int, default=1000)
     ap.add_argument("--cpu-events", type=int, default=10_000_000,
                     help="events of the oracle's timed slice (all host threads)")

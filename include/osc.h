@@ -20,6 +20,9 @@
  * returns before they finish; results are valid once the stream has
  * synchronised.  All device pointers are caller-owned device memory (for
  * example torch tensors' data pointers) and must stay alive until then.
+ * A context's device scratch is ordered by the stream alone while all its
+ * calls use one stream; the first call on a second stream waits once for
+ * the device to go idle, and later calls order the scratch through events.
  * Errors are reported as status codes; nothing aborts the process.
  */
 #ifndef OSC_H

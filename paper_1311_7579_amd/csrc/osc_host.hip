@@ -146,6 +146,11 @@ struct osc_ctx {
     std::vector<osc::SetConsts> consts;
     Scratch slots[kScratchSlots];
     int next_slot = 0;
+    // While every call has used one stream (`sole`), the stream order alone
+    // protects the scratch slots and no event is recorded per call.
+    bool one_stream = true;
+    bool used = false;
+    hipStream_t sole = nullptr;
     double* noalloc = nullptr;      // this device's address of the static scratch array
     bool profiling = false;
     std::vector<ProfRec> prof;
@@ -189,18 +194,35 @@ void prof_mark(hipEvent_t ev, hipStream_t stream)
     if (ev) (void)hipEventRecord(ev, stream);
 }
 
-// Scratch for one call on `stream`: slots are used round-robin; a slot last
-// used on another stream orders the new stream after that use (a wait on
-// its event); on the same stream the stream order already does.
+// Scratch for one call on `stream`: slots are used round-robin.  While the
+// context has seen a single stream, that stream's order already puts every
+// use of a slot after the previous one.  The first call on a second stream
+// waits once for the device to go idle (the first stream may have been
+// destroyed since, so no event can be recorded on it now); from then on
+// every call records the slot's event after its use, and a slot last used
+// on another stream orders the new stream after that use.
 osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scratch** out)
 {
+    if (ctx->one_stream) {
+        if (!ctx->used) {
+            ctx->used = true;
+            ctx->sole = stream;
+        } else if (stream != ctx->sole) {
+            if (hipDeviceSynchronize() != hipSuccess) return OSC_ERR_DEVICE;
+            ctx->one_stream = false;
+        }
+    }
     Scratch& s = ctx->slots[ctx->next_slot];
     ctx->next_slot = (ctx->next_slot + 1) % kScratchSlots;
     if (s.done == nullptr && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return OSC_ERR_DEVICE;
     if (s.cap < bytes) {
         if (s.ptr) {
-            if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) return OSC_ERR_DEVICE;
+            // the slot's last use is on `stream` (one stream) or behind its event
+            const hipError_t e = ctx->one_stream ? hipStreamSynchronize(stream)
+                                 : s.recorded    ? hipEventSynchronize(s.done)
+                                                 : hipSuccess;
+            if (e != hipSuccess) return OSC_ERR_DEVICE;
             if (hipFree(s.ptr) != hipSuccess) return OSC_ERR_DEVICE;
             s.ptr = nullptr;
             s.cap = 0;
@@ -219,8 +241,9 @@ osc_status acquire_scratch(osc_ctx* ctx, size_t bytes, hipStream_t stream, Scrat
     return OSC_OK;
 }
 
-osc_status release_scratch(Scratch* s, hipStream_t stream)
+osc_status release_scratch(osc_ctx* ctx, Scratch* s, hipStream_t stream)
 {
+    if (ctx->one_stream) return OSC_OK;
     if (hipEventRecord(s->done, stream) != hipSuccess) return OSC_ERR_DEVICE;
     s->recorded = true;
     s->last = stream;
@@ -364,7 +387,7 @@ osc_status run_hist(osc_ctx* ctx, int mode, bool write_p, bool mixed, const osc:
                                       static_cast<double*>(s->ptr), stream, lp,
                                       pr ? pr->start : nullptr, pr ? pr->mid : nullptr);
     if (pr) prof_mark(pr->end, stream);
-    st = release_scratch(s, stream);
+    st = release_scratch(ctx, s, stream);
     if (e != hipSuccess) return OSC_ERR_DEVICE;
     return st;
 }
@@ -443,6 +466,9 @@ osc_status osc_destroy(osc_ctx* ctx)
     osc_status st = OSC_OK;
     (void)hipSetDevice(ctx->device);
     drop_profile(ctx);
+    // one stream: it may have been destroyed since its last call, so wait
+    // for the device
+    if (ctx->one_stream && ctx->used && hipDeviceSynchronize() != hipSuccess) st = OSC_ERR_DEVICE;
     for (Scratch& s : ctx->slots) {
         if (s.recorded && hipEventSynchronize(s.done) != hipSuccess) st = OSC_ERR_DEVICE;
         if (s.ptr && hipFree(s.ptr) != hipSuccess) st = OSC_ERR_DEVICE;

@@ -95,6 +95,24 @@ def test_binned_bin_edges_and_specials(osc, ctx):
     np.testing.assert_array_equal(h1, oracle.hist_contract(s.weight * p1, bins, nbins + 2))
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_binned_max_nbins(osc, ctx, precision):
+    """The device's largest bin count: the 16-bit slots cover every row
+    (rows x 8 accumulators < 2^15), and the histogram equals the computed
+    bins' bit for bit."""
+    nb = ctx.max_nbins
+    s = workload.make_sample(50_000, 81)
+    s.e_reco = np.random.default_rng(81).uniform(-0.5, 10.5, s.n)
+    ds = osc.DeviceSample.from_host(s)
+    with ctx.osc_binned_create(ds, nb, 0.0, 10.0) as b:
+        h0, p0, h1, p1 = run(ctx, ds, b, 0, nb, 0.0, 10.0, precision)
+    assert_bits_equal(h1, h0, "hist")
+    assert_bits_equal(p1, p0, "P")
+    bins = oracle.bin_indices(s.e_reco, 0.0, 10.0, nb)
+    np.testing.assert_array_equal(h1, oracle.hist_contract(s.weight * p1, bins, nb + 2))
+    assert (np.bincount(bins, minlength=nb + 2) > 0).sum() > nb // 2   # many rows used
+
+
 def test_binned_invalid_flags_and_empty(osc, ctx):
     """Invalid flag bytes give NaN P and NaN bins in both paths; an empty
     sample gives an all-zero histogram."""

@@ -508,6 +508,38 @@ def test_fill_pdf_deterministic_and_p_optional(osc, ctx):
     np.testing.assert_array_equal(outs[0], outs[2])
 
 
+def test_scratch_order_across_streams(osc, ctx):
+    """A fresh context: back-to-back calls on one stream whose scratch slots
+    grow while earlier calls still run, then calls that alternate with a
+    second stream, with no host wait in between; every histogram equals the
+    one-call result of the shared context bit for bit."""
+    sizes = (1_025, 300_001, 2_000_001, 50_001, 2_000_001, 1_025)
+    samples = {n: osc.DeviceSample.from_host(workload.make_sample(n, 900 + n))
+               for n in set(sizes)}
+    want = {}
+    for n, ds in samples.items():
+        h = torch.empty(52, dtype=torch.float64, device="cuda")
+        ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, None)
+        want[n] = host(h)
+    c = osc.Context(0)
+    try:
+        c.osc_set_params([workload.TABLE1])
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
+        plan = [(n, a) for n in sizes] + [(n, a if k % 2 else b) for k, n in enumerate(sizes)]
+        outs = []
+        torch.cuda.synchronize()
+        for n, st in plan:
+            with torch.cuda.stream(st):
+                h = torch.empty(52, dtype=torch.float64, device="cuda")
+                c.osc_fill_pdf(samples[n], 0, 50, 0.0, 3.0, h, None)
+            outs.append((n, h))
+        torch.cuda.synchronize()
+        for n, h in outs:
+            np.testing.assert_array_equal(host(h), want[n])
+    finally:
+        c.close()
+
+
 def test_fill_pdf_small_and_ragged_against_contract(osc, ctx):
     for n in (1, 65, 1025, 50_001):
         s = workload.make_sample(n, 100 + n)
