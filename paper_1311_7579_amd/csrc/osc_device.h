@@ -303,7 +303,15 @@ struct ConstDensityProb {
 //   sum_k c_k (M - l_j)(M - l_l),  c_k = exp(-i dphi_k) / D_k,
 // so v becomes a2 (M M v) + a1 (M v) + a0 v.  M is the flavour-basis mass
 // matrix of the layer (H0 + A e_e e_e^T, conjugated with A -> -A for
-// antineutrinos); its entries come from the channel table.
+// antineutrinos); its entries come from the channel table.  In the first
+// layer v = e_alpha, so M v is column alpha of M; in the last layer only
+// component beta of the new v is formed.  Both give the same roundings as
+// the full products.
+__device__ __forceinline__ double pick3(uint32_t k, double x0, double x1, double x2)
+{
+    return k == 0u ? x0 : (k == 1u ? x1 : x2);
+}
+
 __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const TileTables& T,
                                                      const LayerPath& lp, double E, uint32_t f)
 {
@@ -345,19 +353,48 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
         const double a2r = iD0 + k1r + k2r, a2i = k1i + k2i;
         const double a1r = -(iD0 * u0 + k1r * u1 + k2r * u2), a1i = -(k1i * u1 + k2i * u2);
         const double a0r = iD0 * w0 + k1r * w1 + k2r * w2, a0i = k1i * w1 + k2i * w2;
-        // y = M v, z = M y
+        // y = M v
         double yr[3], yi[3], zr[3], zi[3];
+        if (layer == 0) {
+            // v = e_alpha: column alpha of H0, plus A on the (e, e) entry
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            double sr = (i == 0) ? A * vr[0] : 0.0, si = (i == 0) ? A * vi[0] : 0.0;
+            for (int i = 0; i < 3; ++i) {
+                yr[i] = pick3(a, hr[i][0], hr[i][1], hr[i][2]);
+                yi[i] = pick3(a, hi[i][0], hi[i][1], hi[i][2]);
+            }
+            yr[0] = fma(A, vr[0], yr[0]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                double sr = (i == 0) ? A * vr[0] : 0.0, si = (i == 0) ? A * vi[0] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    sr = fma(hr[i][j], vr[j], fma(-hi[i][j], vi[j], sr));
+                    si = fma(hr[i][j], vi[j], fma(hi[i][j], vr[j], si));
+                }
+                yr[i] = sr;
+                yi[i] = si;
+            }
+        }
+        if (layer == lp.n - 1) {
+            // component beta of a2 (M y) + a1 y + a0 v: row beta of M
+            double sr = (b == 0u) ? A * yr[0] : 0.0, si = (b == 0u) ? A * yi[0] : 0.0;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                sr = fma(hr[i][j], vr[j], fma(-hi[i][j], vi[j], sr));
-                si = fma(hr[i][j], vi[j], fma(hi[i][j], vr[j], si));
+                const double mr = pick3(b, hr[0][j], hr[1][j], hr[2][j]);
+                const double mi = pick3(b, hi[0][j], hi[1][j], hi[2][j]);
+                sr = fma(mr, yr[j], fma(-mi, yi[j], sr));
+                si = fma(mr, yi[j], fma(mi, yr[j], si));
             }
-            yr[i] = sr;
-            yi[i] = si;
+            const double ybr = pick3(b, yr[0], yr[1], yr[2]), ybi = pick3(b, yi[0], yi[1], yi[2]);
+            const double vbr = pick3(b, vr[0], vr[1], vr[2]), vbi = pick3(b, vi[0], vi[1], vi[2]);
+            const double nr = a2r * sr - a2i * si + a1r * ybr - a1i * ybi + a0r * vbr - a0i * vbi;
+            const double ni = a2r * si + a2i * sr + a1r * ybi + a1i * ybr + a0r * vbi + a0i * vbr;
+            vr[0] = nr;
+            vi[0] = ni;
+            break;
         }
+        // z = M y
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             double sr = (i == 0) ? A * yr[0] : 0.0, si = (i == 0) ? A * yi[0] : 0.0;
@@ -379,9 +416,8 @@ __device__ __forceinline__ double event_prob_layered(const SetConsts& sc, const 
             vi[i] = ni;
         }
     }
-    const double br = b == 0u ? vr[0] : (b == 1u ? vr[1] : vr[2]);
-    const double bi = b == 0u ? vi[0] : (b == 1u ? vi[1] : vi[2]);
-    const double P = br * br + bi * bi;
+    // the last layer left component beta in vr[0], vi[0]
+    const double P = vr[0] * vr[0] + vi[0] * vi[0];
     return __hiloint2double(valid ? __double2hiint(P) : 0x7ff80000, __double2loint(P));
 }
 

@@ -65,7 +65,13 @@ void tile_kernel(
     }
 }
 
-// The same tile body with P through a layered path (FP64 only).
+// The same tile body with P through a layered path (FP64 only).  The event
+// loop stays rolled: the layer loop is large, and 16 unrolled copies of it
+// would not fit the instruction cache.
+#ifndef OSC_LAYERED_ROLL
+#define OSC_LAYERED_ROLL 1
+#endif
+constexpr bool kLayeredRoll = OSC_LAYERED_ROLL;
 template <int MODE, bool WRITE_P>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kLayeredWavesPerSimd)))
 void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConsts bc, int64_t n,
@@ -89,11 +95,11 @@ void layered_tile_kernel(SetConsts sc, SinCosTable sctab, LayerPath lp, BinConst
     const TileArrays t =
         tile_arrays(tile, n, e_true, flags, weight, e_reco, nullptr, nullptr, p_out);
     if (t.n == kTileEvents)
-        tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
-                                                  t.weight, t.e_reco, nullptr, nullptr, t.p_out);
+        tile_events<MODE, WRITE_P, true, kLayeredRoll>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                       t.weight, t.e_reco, nullptr, nullptr, t.p_out);
     else
-        tile_events<MODE, WRITE_P, false, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
-                                                   t.weight, t.e_reco, nullptr, nullptr, t.p_out);
+        tile_events<MODE, WRITE_P, false, kLayeredRoll>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
+                                                        t.weight, t.e_reco, nullptr, nullptr, t.p_out);
 
     if (MODE != kReweight) {
         __syncthreads();
