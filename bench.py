@@ -50,6 +50,21 @@ SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # quotient, floor).
 FLOPS_PER_EVENT = 211
 FLOPS_PER_EVENT_COMPUTED_BINS = 215
+# Layered path, per layer: matter term 1, cubic coefficients 9 and its
+# solution 83 (as above: p 3, seeds 6, Halley 42, Newton 30, third root 2),
+# differences and 1/Q 12, phase scale 1, two sin and cos - 1 52, cos 2,
+# c_k 7, eigenvalue sums and products 6, polynomial coefficients a2, a1, a0
+# 19, y = M v 74, z = M y 74, v = a2 z + a1 y + a0 v 66: 406.  The first
+# layer forms y as column alpha of M (2 instead of 74), the last only
+# component beta of z and v (26 + 22 instead of 74 + 66); per event 1/E 7,
+# |v_beta|^2 3 and the weighted add 2.
+LAYER_FLOPS = 406
+
+
+def layered_flops_per_event(n_layers):
+    return LAYER_FLOPS * n_layers - 72 - 92 + 12
+
+
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz.
 FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
@@ -408,10 +423,15 @@ def layered_form(osc, ctx, n=10_000_000, reps=10):
     ev_ms, ev_n, _, _ = ctx.osc_profile_read()
     ctx.osc_profile_enable(False)
     kernel_ms = ev_ms / max(ev_n, 1)
+    flops = layered_flops_per_event(len(earth))
+    tflops = flops * n / (kernel_ms * 1e-3) / 1e12
     return {"config": "5-layer Earth path (11600 km), 1e7 events, E log-uniform 0.5-20 GeV, "
                       "all channels, FP64, 50 bins",
             "layers": 5, "ms_per_call": wall_ms, "kernel_ms": kernel_ms,
-            "evals_per_s": n / (wall_ms * 1e-3), "layer_evals_per_s": 5 * n / (kernel_ms * 1e-3)}
+            "evals_per_s": n / (wall_ms * 1e-3), "layer_evals_per_s": 5 * n / (kernel_ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / FP64_PEAK_TFLOPS,
+                         "flops_per_event": flops, "kernel": "layered_tile_kernel<kPdf, no P>"}}
 
 
 def batched_form(osc, ctx, reps=5):
