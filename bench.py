@@ -80,12 +80,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 92830.6, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 82505.4, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 92829.8, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 82534.1, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     "valu_per_event": 176.8,
     "classes_per_event": {"fp64": 130.5, "fp64_trans": 3.0, "fp32": 12.0, "fp32_trans": 4.0,
                           "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 15.25},
-    "source_sha256": "0d6be9d56f092f30254538196819a4e51a931ca6a732071859da53ff39d4e8dc",
+    "source_sha256": "6a6051a8a34fc126b51267a4b7bafacf86411d942a974c24077006a859e9fbd4",
 }
 # Issue time of one wave instruction on one SIMD, measured on the box with
 # probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32
@@ -332,6 +332,16 @@ def precision_form(osc, ctx, ds, binned, n_sets=64, set_seed=3, n_oracle=100_000
     return out
 
 
+def settle(fn, seconds=SETTLE_S * 3):
+    """Untimed calls of fn for `seconds` (the engine clock ramps up again
+    after the host-side set-up of a form)."""
+    import torch
+    t = time.perf_counter()
+    while time.perf_counter() - t < seconds:
+        fn()
+        torch.cuda.synchronize()
+
+
 def bincentre_form(osc, ctx, s, ds, ebe_ms, calls=200):
     """Sec. 1.1.1's approximate alternative on the same events: a migration
     template over 200 true-energy bins (0.1-10.1 GeV) and the 50 reco bins,
@@ -348,9 +358,7 @@ def bincentre_form(osc, ctx, s, ds, ebe_ms, calls=200):
     tp = osc.Template(ctx, ds, nt, lo_t, hi_t, NBINS, LO, HI)
     build_ms = (time.perf_counter() - t0) * 1e3
     h = torch.empty(NBINS + 2, dtype=torch.float64, device="cuda")
-    for _ in range(10):
-        tp.fill_pdf(0, h)
-    torch.cuda.synchronize()
+    settle(lambda: tp.fill_pdf(0, h))
     t0 = time.perf_counter()
     for _ in range(calls):
         tp.fill_pdf(0, h)
@@ -394,7 +402,7 @@ def bincentre_form(osc, ctx, s, ds, ebe_ms, calls=200):
     }
 
 
-def layered_form(osc, ctx, n=10_000_000, reps=10):
+def layered_form(osc, ctx, n=10_000_000, reps=20):
     """Piecewise-constant matter: a five-layer path through the Earth
     (crust, mantle, core, mantle, crust; 11600 km) for an atmospheric-like
     sample of 1e7 events, E log-uniform on [0.5, 20] GeV, every channel,
@@ -411,9 +419,7 @@ def layered_form(osc, ctx, n=10_000_000, reps=10):
     x = np.maximum(e * rng.normal(1.0, 0.1, n), 1e-12)
     ds = osc.DeviceSample.from_host(workload.Sample(e, f, w, x))
     h = torch.empty(52, dtype=torch.float64, device="cuda")
-    for _ in range(2):
-        ctx.osc_fill_pdf_layered(ds, earth, 0, 50, 0.0, 20.0, h)
-    torch.cuda.synchronize()
+    settle(lambda: ctx.osc_fill_pdf_layered(ds, earth, 0, 50, 0.0, 20.0, h))
     ctx.osc_profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(reps):
