@@ -226,7 +226,10 @@ void dispatch_loop(osc_server* sv)
                 std::max<int64_t>(sv->stats.peak_scratch_bytes, int64_t(sv->arena.used()));
             const osc_status st = launch(sv, *free_slot, r);
             if (st != OSC_OK) {
-                // never started: fail the request and free its resources
+                // fail the request and free its resources; kernels that were
+                // enqueued before the failure may still use the scratch, so
+                // the slot's stream drains first
+                (void)hipStreamSynchronize(free_slot->stream);
                 r.status = st;
                 r.done = true;
                 r.t_done = now_s();
