@@ -254,7 +254,7 @@ def cpu_baseline(sample, n_all, n_one, reps=5):
         "sample": f"median of {reps} passes over the first {n_all} events of the 1e7-event "
                   f"workload (fill_pdf with P written), {threads} OpenMP threads; oracle source "
                   f"built with gcc -O3 -march=native -ffp-contract=off on this host "
-                  f"({all_s:.1f} s in all)",
+                  f"({all_s:.1f} s wall in all, about {all_s * threads:.0f} thread-seconds)",
         "single_core_value": one_rate,
         "single_core_sample": f"median of {reps} passes over the first {n_one} events, "
                               f"1 thread ({one_s:.1f} s in all)",

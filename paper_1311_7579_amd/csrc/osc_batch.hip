@@ -95,11 +95,9 @@ __global__ void reset_queue(unsigned* queue)
 
 template <bool MIXED>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kBatchWavesPerSimd)))
-void batch_kernel(BatchArgs a, SinCosTable sctab,
-                                                           const BatchSampleDev* __restrict__ samples,
-                                                           const SetConsts* __restrict__ sets,
-                                                           double* __restrict__ partial,
-                                                           unsigned* __restrict__ queue)
+void batch_kernel(BatchArgs a, SinCosTable sctab, const BatchSampleDev* __restrict__ samples,
+                  const SetConsts* __restrict__ sets, double* __restrict__ partial,
+                  unsigned* __restrict__ queue)
 {
     extern __shared__ double hist[];
     __shared__ TileTables tabs;
