@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from paper_1311_7579_amd import workload
-from helpers import P_TOL, MIXED_TOL, assert_bits_equal, hist_tolerance
+from helpers import P_TOL, MIXED_TOL, MIXED_TOL_C3, assert_bits_equal, hist_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +93,30 @@ def test_binned_bin_edges_and_specials(osc, ctx):
     assert_bits_equal(h1, h0, "hist")
     bins = oracle.bin_indices(x, lo, hi, nbins)
     np.testing.assert_array_equal(h1, oracle.hist_contract(s.weight * p1, bins, nbins + 2))
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_binned_benchmark_workload_full_size(osc, ctx, precision):
+    """The benchmark step itself: 1e7 events (seed 1), Table 1, 50 bins on
+    [0, 3] GeV, P written, as bench.py launches it.  Every P against the
+    oracle, the histogram within the carried tolerance, and bit-exact
+    against the contract replayed on the GPU's own P."""
+    s = workload.make_sample(10_000_000, 1)
+    ds = osc.DeviceSample.from_host(s)
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    p = torch.empty(s.n, dtype=torch.float64, device="cuda")
+    with ctx.osc_binned_create(ds, 50, 0.0, 3.0) as b:
+        ctx.osc_fill_pdf_binned(b, 0, h, p, precision=precision)
+        torch.cuda.synchronize()
+    h, p = h.cpu().numpy(), p.cpu().numpy()
+    hist_o, p_o = oracle.fill_pdf(workload.TABLE1, s.L_km, s.rho_gcc, s.Ye, s.e_true, s.flags,
+                                  s.weight, s.e_reco, 50, 0.0, 3.0)
+    tol_p = P_TOL if precision == 0 else MIXED_TOL_C3
+    assert np.abs(p - p_o).max() <= tol_p
+    bins = oracle.bin_indices(s.e_reco, 0.0, 3.0, 50)
+    tol = hist_tolerance(s.weight, s.weight * p_o, bins, 52, s.n, p_tol=tol_p)
+    assert (np.abs(h - hist_o) <= tol).all()
+    np.testing.assert_array_equal(h, oracle.hist_contract(s.weight * p, bins, 52))
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])

@@ -110,6 +110,35 @@ def test_fill_pdf_layered_histogram(osc, ctx, n):
     np.testing.assert_array_equal(host(h), oracle.hist_contract(s.weight * P, bins, 42))
 
 
+def test_layered_benchmark_workload_full_size(osc, ctx):
+    """The layered benchmark form as bench.py launches it: 1e7 events (E
+    log-uniform on 0.5-20 GeV, every channel, 40 % antineutrinos, seed 61)
+    through the five-layer Earth path, 50 bins on [0, 20] GeV, no P
+    written.  Its histogram equals the P-writing call's bit for bit and
+    the contract replayed on that P; P is checked against the oracle on
+    every 101st event."""
+    n = 10_000_000
+    rng = np.random.default_rng(61)
+    e = 10 ** rng.uniform(np.log10(0.5), np.log10(20.0), n)
+    f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), rng.random(n) < 0.4)
+    w = rng.uniform(0.5, 1.5, n)
+    x = np.maximum(e * rng.normal(1.0, 0.1, n), 1e-12)
+    s = workload.Sample(e, f, w, x)
+    ds = osc.DeviceSample.from_host(s)
+    h0 = torch.empty(52, dtype=torch.float64, device="cuda")
+    h1 = torch.empty(52, dtype=torch.float64, device="cuda")
+    p = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.osc_fill_pdf_layered(ds, EARTH, 0, 50, 0.0, 20.0, h0)
+    ctx.osc_fill_pdf_layered(ds, EARTH, 0, 50, 0.0, 20.0, h1, p)
+    h0, h1, P = host(h0), host(h1), host(p)
+    np.testing.assert_array_equal(h0, h1)
+    bins = bins_np(s.e_reco, 0.0, 20.0, 50)
+    np.testing.assert_array_equal(h0, oracle.hist_contract(s.weight * P, bins, 52))
+    idx = np.arange(0, n, 101)
+    want = oracle.prob_layered_batch(SETS[0], EARTH, s.e_true[idx], s.flags[idx])
+    assert np.abs(P[idx] - want).max() <= P_TOL
+
+
 def test_invalid_layers(osc, ctx):
     s = all_channel_sample(10, 1)
     ds = osc.DeviceSample.from_host(s)
