@@ -100,10 +100,10 @@ void batch_kernel(BatchArgs a, SinCosTable sctab, const BatchSampleDev* __restri
                   unsigned* __restrict__ queue)
 {
     extern __shared__ double hist[];
-    __shared__ TileTables tabs;
+    __shared__ Tables<MIXED> tabs;
     const int lane = threadIdx.x;
     const int nbt = a.nbt;
-    if (!MIXED) load_sincos(sctab, tabs, lane);   // read after the first barrier below
+    if constexpr (!MIXED) load_sincos(sctab, tabs, lane);   // read after the first barrier below
 
     const int64_t G = gridDim.x, b = blockIdx.x;
     int64_t item, end, stride = 0, base = 0;
@@ -142,7 +142,7 @@ void batch_kernel(BatchArgs a, SinCosTable sctab, const BatchSampleDev* __restri
         for (int set = int(g) * a.sets_per_item; set < set_end; ++set) {
             const SetConsts& sc = sets[set];
             __syncthreads();   // the previous set's table and histogram are read
-            load_tab(sc, tabs, lane);
+            load_tab<MIXED>(sc, tabs, lane);
             hist_zero(hist, lane, nbt);
             __syncthreads();
             const ConstDensityProb<MIXED> prob{&sc, &tabs, S.pc.kA, S.pc.kL};

@@ -5,6 +5,8 @@
 // one bit for bit.
 #pragma once
 
+#include <type_traits>
+
 #include "osc_internal.h"
 
 namespace osc {
@@ -211,22 +213,31 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
 // exp(-i phi_0) drops out of |.|^2, so only the differences phi_k - phi_0
 // are formed.
 template <bool MIXED>
-__device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTables& T, double kA,
-                                             double kL, double E, uint32_t f)
+__device__ __forceinline__ double event_prob(const SetConsts& sc, const Tables<MIXED>& T,
+                                             double kA, double kL, double E, uint32_t f)
 {
+    using Entry = std::conditional_t<MIXED, ChanF, ChanL>;
+    using Real = std::conditional_t<MIXED, float, double>;
     // flag byte (alpha bits 0-1, beta bits 2-3, antineutrino bit 4) -> the
     // channel entry (conjugated for antineutrinos) and the sign of A
     const FlagInfo fl = T.flag[min(f, uint32_t(kFlagEntries - 1))];
-    const ChanL c = *reinterpret_cast<const ChanL*>(
+    const Entry c = *reinterpret_cast<const Entry*>(
         reinterpret_cast<const unsigned char*>(T.ch) + fl.ch_off);
     const double A = flip_sign(kA * E, fl.sign);
-    const double dba = c.dba;   // [alpha = beta]; NaN for an invalid flag byte
+    const Real dba = c.dba;   // [alpha = beta]; NaN for an invalid flag byte
 
-    // amplitude inputs: M_ba and (M^2)_ba
-    const double mre = fma(A, c.dee, c.m_re);
-    const double mim = c.m_im;
-    const double m2re = fma(A, fma(A, c.dee, c.g_re), c.m2_re);
-    const double m2im = fma(A, c.g_im, c.m2_im);
+    // amplitude inputs: M_ba and (M^2)_ba (FP32 in the mixed tier)
+    const auto mad = [](Real a, Real b, Real d) -> Real {
+        if constexpr (MIXED)
+            return __builtin_fmaf(a, b, d);
+        else
+            return __builtin_fma(a, b, d);
+    };
+    const Real Ar = Real(A);
+    const Real mre = mad(Ar, c.dee, c.m_re);
+    const Real mim = c.m_im;
+    const Real m2re = mad(Ar, mad(Ar, c.dee, c.g_re), c.m2_re);
+    const Real m2im = mad(Ar, c.g_im, c.m2_im);
 
     // matter eigenvalues (FP64 in every tier)
     double l0, l1, l2;
@@ -265,8 +276,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
         phase_sincos_mixed(-d01, ph, s1, c1);
         phase_sincos_mixed(-d02, ph, s2, c2);
         // amplitude assembly in FP32 from FP32-rounded inputs
-        const float fmre = float(mre), fmim = float(mim), fm2re = float(m2re), fm2im = float(m2im);
-        const float fdba = float(dba);
+        const float fmre = mre, fmim = mim, fm2re = m2re, fm2im = m2im;
+        const float fdba = dba;
         const float fu1 = float(u1), fu2 = float(u2);
         const float fv1 = float(v1), fv2 = float(v2);
         const float fi1 = float(iD1), fi2 = float(iD2);
@@ -287,7 +298,7 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const TileTabl
 template <bool MIXED>
 struct ConstDensityProb {
     const SetConsts* sc;
-    const TileTables* tabs;
+    const Tables<MIXED>* tabs;
     double kA, kL;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
@@ -778,9 +789,12 @@ __device__ __forceinline__ TileArrays tile_arrays(int64_t tile, int64_t n, const
 }
 
 // Build the channel and flag tables of a parameter set in LDS (lanes 0-31
-// of the block's first wave; the caller's barrier publishes them).
-__device__ __forceinline__ void load_tab(const SetConsts& sc, TileTables& T, int lane)
+// of the block's first wave; the caller's barrier publishes them).  The
+// mixed tier's tables hold the entries rounded to FP32.
+template <bool MIXED = false>
+__device__ __forceinline__ void load_tab(const SetConsts& sc, Tables<MIXED>& T, int lane)
 {
+    using Entry = std::conditional_t<MIXED, ChanF, ChanL>;
     if (lane < kLdsChannels) {
         ChanL e;
         if (lane < kInvalidChannel) {
@@ -799,7 +813,11 @@ __device__ __forceinline__ void load_tab(const SetConsts& sc, TileTables& T, int
             e.m_re = e.m_im = e.m2_re = e.m2_im = e.g_re = e.g_im = e.dee = 0.0;
             e.dba = __builtin_nan("");
         }
-        T.ch[lane] = e;
+        if constexpr (MIXED)
+            T.ch[lane] = ChanF{float(e.m_re), float(e.m_im), float(e.m2_re), float(e.m2_im),
+                               float(e.g_re), float(e.g_im), float(e.dee), float(e.dba)};
+        else
+            T.ch[lane] = e;
     }
     if (lane < kFlagEntries) {
         const uint32_t f = uint32_t(lane);
@@ -808,7 +826,7 @@ __device__ __forceinline__ void load_tab(const SetConsts& sc, TileTables& T, int
         const uint32_t entry =
             valid ? (f & 3u) + 3u * ((f >> 2) & 3u) + anti * uint32_t(kChannels)
                   : uint32_t(kInvalidChannel);
-        T.flag[lane] = FlagInfo{entry * uint32_t(sizeof(ChanL)), valid && anti ? 0x80000000u : 0u};
+        T.flag[lane] = FlagInfo{entry * uint32_t(sizeof(Entry)), valid && anti ? 0x80000000u : 0u};
     }
 }
 

@@ -184,7 +184,7 @@ constexpr int kLdsChannels = 2 * kChannels + 1;
 constexpr int kInvalidChannel = 2 * kChannels;
 constexpr int kFlagEntries = 32;
 struct FlagInfo {
-    uint32_t ch_off;   // byte offset into TileTables::ch
+    uint32_t ch_off;   // byte offset into the table's ch array
     uint32_t sign;     // 0 or 0x80000000: the sign bit of A
 };
 struct TileTables {
@@ -192,5 +192,30 @@ struct TileTables {
     FlagInfo flag[kFlagEntries];
     SinCosL sct[64];
 };
+
+// The FP32-mixed tier assembles the amplitude in FP32 from the same channel
+// entries rounded to FP32 (M_ba and (M^2)_ba are then formed from them in
+// FP32), and its phases use the hardware sine and cosine, so its tables
+// hold FP32 channel entries and no sin/cos anchors.
+struct ChanF {
+    float m_re, m_im;
+    float m2_re, m2_im;
+    float g_re, g_im;
+    float dee, dba;
+};
+struct TileTablesMixed {
+    ChanF ch[kLdsChannels];
+    FlagInfo flag[kFlagEntries];
+};
+template <bool MIXED>
+struct TablesOf {
+    using type = TileTables;
+};
+template <>
+struct TablesOf<true> {
+    using type = TileTablesMixed;
+};
+template <bool MIXED>
+using Tables = typename TablesOf<MIXED>::type;
 
 }  // namespace osc

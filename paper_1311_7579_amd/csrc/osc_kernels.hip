@@ -37,15 +37,15 @@ void tile_kernel(
     double* __restrict__ p_out, double* __restrict__ partial)
 {
     extern __shared__ double hist[];
-    __shared__ TileTables tabs;
+    __shared__ Tables<MIXED> tabs;
 
     const int lane = threadIdx.x;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int nbt = bc.nb + 2;
 
     if (MODE != kHist) {
-        load_tab(sc, tabs, lane);
-        if (!MIXED) load_sincos(sctab, tabs, lane);
+        load_tab<MIXED>(sc, tabs, lane);
+        if constexpr (!MIXED) load_sincos(sctab, tabs, lane);
     }
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
