@@ -80,12 +80,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 92829.8, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 82534.1, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "fetch_kib": 92835.5, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 82538.7, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
     "valu_per_event": 176.8,
     "classes_per_event": {"fp64": 130.5, "fp64_trans": 3.0, "fp32": 12.0, "fp32_trans": 4.0,
                           "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 15.25},
-    "source_sha256": "6a6051a8a34fc126b51267a4b7bafacf86411d942a974c24077006a859e9fbd4",
+    "source_sha256": "d0afcff3ed2b3227281378aa2c05a826e7711d71f3f4e5a4ea5a9ecbb28f3d39",
 }
 # Issue time of one wave instruction on one SIMD, measured on the box with
 # probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32
