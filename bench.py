@@ -16,7 +16,6 @@ stream, and the CPU oracle timed on a bounded slice of the same events.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time

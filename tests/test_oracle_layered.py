@@ -3,7 +3,6 @@ reduces to the constant-density path, a split constant layer and split
 vacuum reduce to the unsplit path, unitarity, time reversal of the layer
 order at delta = 0, and a brute-force product of matrix exponentials."""
 import numpy as np
-import pytest
 from scipy.linalg import expm
 
 import oracle
