@@ -37,7 +37,9 @@ def test_header_declares_the_entry_points():
                  "osc_batch_tune", "osc_server_create", "osc_server_submit", "osc_server_wait",
                  "osc_server_set_data", "osc_server_poll", "osc_reweight_layered",
                  "osc_fill_pdf_layered", "osc_template_create", "osc_template_copy",
-                 "osc_template_destroy", "osc_fill_pdf_bincentre", "osc_validate_sample"):
+                 "osc_template_destroy", "osc_fill_pdf_bincentre", "osc_validate_sample",
+                 "osc_binned_create", "osc_binned_destroy", "osc_fill_pdf_binned",
+                 "osc_fill_pdf_noalloc"):
         assert want in names
 
 
