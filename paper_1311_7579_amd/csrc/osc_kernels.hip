@@ -30,7 +30,8 @@ using namespace dev;
 template <int MODE, bool WRITE_P, bool MIXED = false>
 __global__ __launch_bounds__(kTileLanes) __attribute__((amdgpu_waves_per_eu(kTileWavesPerSimd)))
 void tile_kernel(
-    SetConsts sc, SinCosTable sctab, PathConsts pc, BinConsts bc, int64_t n, int64_t ntiles,
+    SetConsts sc, SinCosTable sctab, PathConsts pc, BinConsts bc, int64_t n,
+    [[maybe_unused]] int64_t ntiles,
     const double* __restrict__ e_true, const uint8_t* __restrict__ flags,
     const double* __restrict__ weight, const double* __restrict__ e_reco,
     const uint16_t* __restrict__ bins, const double* __restrict__ value,
