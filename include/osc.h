@@ -135,11 +135,15 @@ osc_status osc_validate_sample(osc_ctx* ctx, const osc_sample* sample, int64_t* 
  * `sample` under parameter set `set` to p_out (device, n FP64 entries,
  * event order).  weight and e_reco are not read.
  * Accuracy domain (all per-event entry points): P is within about 1e-12 of
- * the exact value (plus 2^-53 |A| / (smallest eigenvalue distance) from
- * the amplitude's own cancellation) for matter terms |A| = K_A Ye rho E up
- * to about 1 eV^2 with mixing angles near the measured ones (Table 1:
- * E rho Ye up to ~6500 GeV g/cm^3), and up to about 0.04 eV^2 for
- * arbitrary angles.  Beyond that the FP32 seeds of the eigenvalue solver
+ * the exact value, plus 2^-53 |A| / gap from the amplitude's own
+ * cancellation and 4 * 2^-53 * phi * (1 + spread / gap) from the FP64
+ * rounding of the largest phase difference phi (radians), amplified by
+ * the eigenvalues' conditioning (gap and spread: the smallest and largest
+ * distance between the eigenvalues of the matter Hamiltonian; the phase
+ * term reaches 1e-12 where phi * (1 + spread / gap) reaches about 2e3),
+ * for matter terms |A| = K_A Ye rho E up to about 1 eV^2 with mixing
+ * angles near the measured ones (Table 1: E rho Ye up to ~6500 GeV
+ * g/cm^3), and up to about 0.04 eV^2 for arbitrary angles.  Beyond that the FP32 seeds of the eigenvalue solver
  * can no longer resolve the two roots that stay near the vacuum masses and
  * P is not reliable. */
 osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
