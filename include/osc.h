@@ -51,8 +51,9 @@ typedef enum {
                             smallest distance, not to the last bit).  Measured
                             |P - P_exact|: <= 1.5e-6 for Table 1-like sets at
                             295 km, <= 6e-6 to 2500 km, <= 1.8e-5 for any
-                            angles at E <= 20 GeV; it grows with the matter
-                            term, to ~1e-4 at |A| ~ 0.07 eV^2             */
+                            angles at E <= 20 GeV through rho <= 3 g/cm^3;
+                            it grows with the matter term, to ~1e-4 at
+                            |A| ~ 0.07 eV^2                                */
 } osc_precision;
 
 /* Opaque context bound to one device: holds the parameter sets and the
