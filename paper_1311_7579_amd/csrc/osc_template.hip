@@ -135,7 +135,11 @@ __global__ __launch_bounds__(64) void centre_probs_kernel(SetConsts sc, SinCosTa
 }
 
 // hist[r] for one reconstructed bin per wave: lane l adds the terms
-// k = l, l + 64, ... in ascending k, then the wave's binary tree.
+// k = l, l + 64, ... in ascending k, then the wave's binary tree.  The
+// operands of kContractBatch consecutive terms are loaded before any of
+// them is added, so the loads overlap; the additions keep their order.
+constexpr int kContractBatch = 8;
+
 __global__ __launch_bounds__(64) void bincentre_contract_kernel(const double* __restrict__ T,
                                                                 const double* __restrict__ P,
                                                                 int64_t K,
@@ -145,7 +149,22 @@ __global__ __launch_bounds__(64) void bincentre_contract_kernel(const double* __
     const int lane = threadIdx.x;
     const double* row = T + int64_t(r) * K;
     double acc = 0.0;
-    for (int64_t k = lane; k < K; k += 64) {
+    int64_t k = lane;
+    for (; k + (kContractBatch - 1) * 64 < K; k += kContractBatch * 64) {
+        double t[kContractBatch], p[kContractBatch];
+#pragma unroll
+        for (int j = 0; j < kContractBatch; ++j) {
+            t[j] = row[k + j * 64];
+            p[j] = P[k + j * 64];
+        }
+#pragma unroll
+        for (int j = 0; j < kContractBatch; ++j) {
+#pragma clang fp contract(off)
+            const double term = t[j] * p[j];
+            acc = acc + term;
+        }
+    }
+    for (; k < K; k += 64) {
 #pragma clang fp contract(off)
         const double term = row[k] * P[k];
         acc = acc + term;
