@@ -84,3 +84,31 @@ def test_random_configurations_within_bound(osc, ctx, seed):
         assert ratio.max() <= 1.0, (k, p, L, rho, float(ratio.max()))
         worst = max(worst, float(ratio.max()))
     print(f"worst error / bound over 60 configurations: {worst:.3g}")
+
+
+def test_mixed_tier_envelope(osc, ctx):
+    """The FP32-mixed tier over the same random domain stays within the
+    envelope the header states: about 1e-4 at worst (large matter terms
+    with arbitrary angles), checked with a factor 3 of margin, and within
+    4e-5 wherever E <= 20 GeV, rho <= 3 g/cm^3 and L <= 2500 km."""
+    rng = np.random.default_rng(5)
+    n = 100_000
+    h = torch.empty(52, dtype=torch.float64, device="cuda")
+    for k in range(60):
+        seed_k = int(rng.integers(1 << 30))
+        p = (workload.make_param_sets(1, seed_k)[0] if k % 2 == 0
+             else workload.make_random_physics_sets(1, seed_k)[0])
+        L = float(rng.uniform(0.0, 13000.0))
+        rho = float(rng.choice([0.0, rng.uniform(0.5, 13.0)]))
+        ye = float(rng.uniform(0.45, 0.5))
+        e = 10 ** rng.uniform(math.log10(0.05), 2.0, n)
+        f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), rng.random(n) < 0.5)
+        s = workload.Sample(e, f, np.ones(n), e.copy(), L_km=L, rho_gcc=rho, Ye=ye)
+        ctx.osc_set_params([p])
+        ds = osc.DeviceSample.from_host(s)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, out, precision=osc.OSC_FP32_MIXED)
+        d = np.abs(out.cpu().numpy() - oracle.prob_batch(p, L, rho, ye, e, f))
+        assert d.max() <= 3e-4, (k, p, L, rho, float(d.max()))
+        if rho <= 3.0 and L <= 2500.0:
+            assert d[e <= 20.0].max() <= 4e-5, (k, p, L, rho, float(d[e <= 20.0].max()))
