@@ -84,7 +84,7 @@ COUNTER_TRAFFIC = {
     "valu_per_event": 176.8,
     "classes_per_event": {"fp64": 130.5, "fp64_trans": 3.0, "fp32": 12.0, "fp32_trans": 4.0,
                           "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 15.25},
-    "source_sha256": "657a37e3033b789c0b7bbe828ffc2aa7b9420fe02365deef81d74de7db80f9ae",
+    "source_sha256": "e6c8748e16ee10193062474fcd99b7e6bacb1f95d9f5003bb469209d29db5b01",
 }
 # Issue time of one wave instruction on one SIMD, measured on the box with
 # probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32

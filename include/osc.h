@@ -48,12 +48,14 @@ typedef enum {
     OSC_FP64 = 0,        /* every step in FP64 (the paper's precision, Sec. 2.1) */
     OSC_FP32_MIXED = 1   /* FP64 eigenvalues and phases, FP32 amplitude assembly
                             (eigenvalues refined until within ~1e-11 of their
-                            smallest distance, not to the last bit).  Measured
-                            |P - P_exact|: <= 1.5e-6 for Table 1-like sets at
-                            295 km, <= 6e-6 to 2500 km, <= 1.8e-5 for any
-                            angles at E <= 20 GeV through rho <= 3 g/cm^3;
-                            it grows with the matter term, to ~1e-4 at
-                            |A| ~ 0.07 eV^2                                */
+                            smallest distance, not to the last bit; waves
+                            with |A| > 0.01 eV^2 assemble in FP64).
+                            Measured |P - P_exact|: <= 1.5e-6 for Table
+                            1-like sets at 295 km, <= 6e-6 to 2500 km and
+                            for near-measured angles anywhere, <= 1.8e-5
+                            for any angles at E <= 20 GeV through rho <= 3
+                            g/cm^3, ~5e-5 at worst (any angles, long L/E
+                            near the solar resonance)                      */
 } osc_precision;
 
 /* Opaque context bound to one device: holds the parameter sets and the

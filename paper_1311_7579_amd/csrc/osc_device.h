@@ -143,6 +143,9 @@ __device__ __forceinline__ double sgpr_value(double v)
 // (2^-12)^3 ~ 1.5e-11 of that distance, far below what the FP32 amplitude
 // assembly resolves, and the phases stay within ~1e-8 rad up to 1e3 rad.
 constexpr double kHalleyOnly = 0x1p-12;
+// FP32-mixed tier: waves with a matter term above this (eV^2, about 4
+// times the largest vacuum splitting) assemble the amplitude in FP64.
+constexpr double kMixedWideA = 0.01;
 
 template <bool HALLEY_ONLY = false>
 __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, double qh,
@@ -275,6 +278,26 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Tables<M
         float s1, c1, s2, c2;
         phase_sincos_mixed(-d01, ph, s1, c1);
         phase_sincos_mixed(-d02, ph, s2, c2);
+        if (__any(__builtin_fabs(A) > kMixedWideA)) {
+            // Matter terms well above the vacuum splittings: the projector
+            // numerators cancel over about |A| / dm^2_31, beyond what FP32
+            // resolves, so such waves form them and the sum in FP64 (from
+            // the same FP32 channel entries and FP32 phases).
+            const double d_dee = c.dee, d_dba = c.dba;
+            const double d_mre = fma(A, d_dee, double(c.m_re));
+            const double d_mim = c.m_im;
+            const double d_m2re = fma(A, fma(A, d_dee, double(c.g_re)), double(c.m2_re));
+            const double d_m2im = fma(A, double(c.g_im), double(c.m2_im));
+            const double x1r = fma(v1, d_dba, fma(-u1, d_mre, d_m2re)) * iD1;
+            const double x1i = fma(-u1, d_mim, d_m2im) * iD1;
+            const double x2r = fma(v2, d_dba, fma(-u2, d_mre, d_m2re)) * iD2;
+            const double x2i = fma(-u2, d_mim, d_m2im) * iD2;
+            const double e1 = double(c1) - 1.0, e2 = double(c2) - 1.0;
+            const double ds1 = s1, ds2 = s2;
+            const double sr = d_dba + e1 * x1r + ds1 * x1i + e2 * x2r + ds2 * x2i;
+            const double si = e1 * x1i - ds1 * x1r + e2 * x2i - ds2 * x2r;
+            return sr * sr + si * si;
+        }
         // amplitude assembly in FP32 from FP32-rounded inputs
         const float fmre = mre, fmim = mim, fm2re = m2re, fm2im = m2im;
         const float fdba = dba;

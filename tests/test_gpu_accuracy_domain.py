@@ -88,8 +88,9 @@ def test_random_configurations_within_bound(osc, ctx, seed):
 
 def test_mixed_tier_envelope(osc, ctx):
     """The FP32-mixed tier over the same random domain stays within the
-    envelope the header states: about 1e-4 at worst (large matter terms
-    with arbitrary angles), checked with a factor 3 of margin, and within
+    envelope the header states: about 5e-5 at worst (arbitrary angles,
+    long L/E near the solar resonance), checked with a factor 3 of margin,
+    and within
     4e-5 wherever E <= 20 GeV, rho <= 3 g/cm^3 and L <= 2500 km."""
     rng = np.random.default_rng(5)
     n = 100_000
@@ -109,6 +110,6 @@ def test_mixed_tier_envelope(osc, ctx):
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, out, precision=osc.OSC_FP32_MIXED)
         d = np.abs(out.cpu().numpy() - oracle.prob_batch(p, L, rho, ye, e, f))
-        assert d.max() <= 3e-4, (k, p, L, rho, float(d.max()))
+        assert d.max() <= 1.5e-4, (k, p, L, rho, float(d.max()))
         if rho <= 3.0 and L <= 2500.0:
             assert d[e <= 20.0].max() <= 4e-5, (k, p, L, rho, float(d[e <= 20.0].max()))
