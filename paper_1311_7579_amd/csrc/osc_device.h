@@ -134,15 +134,24 @@ __device__ __forceinline__ double sgpr_value(double v)
 // solution x = tr/3 + (2/3) sqrt(p) cos(theta - 2 pi k / 3),
 // theta = acos(q / (2 p^1.5)) / 3 (p = tr^2 - 3 c1; qh = q / 2 with
 // q = 2 tr^3 - 9 tr c1 + 27 det is passed in), each refined in FP64 by one
-// Halley and one Newton step on f; the third root follows from the trace.  The two roots'
-// divisions of each step share one reciprocal: 1/a = b / (a b),
-// 1/b = a / (a b).
+// Halley step on f with its third-order error term added back; the third
+// root follows from the trace.  The two roots' divisions of each step
+// share one reciprocal: 1/a = b / (a b), 1/b = a / (a b).
+// The seeds err by about 1e-4 of the roots' spread, so relative to the
+// smallest root distance they worsen as two roots close in.  With
+// r = q / (2 p^1.5) = cos 3 theta, that distance over the spread is about
+// sqrt((1 - |r|) / 3.4), and a wave where some lane has 1 - |r| below
+// kNearDegenerate (distance under ~0.85 % of the spread: near a level
+// crossing, or a matter term far above the vacuum splittings) adds one
+// Newton step.  Elsewhere the corrected Halley step leaves the roots within
+// ~1e-14 of their smallest distance, as Halley and Newton together do.
 // HALLEY_ONLY (the FP32-mixed tier): a wave skips the Newton step when
 // every lane's Halley corrections were at most 2^-12 of its smallest root
 // distance.  Halley converges cubically, so the roots are then within about
 // (2^-12)^3 ~ 1.5e-11 of that distance, far below what the FP32 amplitude
 // assembly resolves, and the phases stay within ~1e-8 rad up to 1e3 rad.
 constexpr double kHalleyOnly = 0x1p-12;
+constexpr float kNearDegenerate = 0x1p-12f;
 // FP32-mixed tier: waves with a matter term above this (eV^2, about 4
 // times the largest vacuum splitting) assemble the amplitude in FP64.
 constexpr double kMixedWideA = 0.01;
@@ -171,12 +180,28 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
         const double g0 = fma(x0, fma(three, x0, -tr2), c1);
         const double g1 = fma(x1, fma(three, x1, -tr2), c1);
         // -f f''/2 = f (tr - 3x)
-        const double d0 = fma(g0, g0, f0 * fma(-three, x0, tr));
-        const double d1 = fma(g1, g1, f1 * fma(-three, x1, tr));
+        const double m0 = fma(-three, x0, tr), m1 = fma(-three, x1, tr);
+        const double d0 = fma(g0, g0, f0 * m0);
+        const double d1 = fma(g1, g1, f1 * m1);
         const double r = recip_coarse(d0 * d1);
         if constexpr (!HALLEY_ONLY) {
-            x0 -= (f0 * g0) * (d1 * r);
-            x1 -= (f1 * g1) * (d0 * r);
+            // the Halley step h and its leading error term: for this cubic
+            // the root lies C h^3 beyond x - h, C = (f' - (3x - tr)^2) / f'^2
+            // (to leading order; h is then the seed's error), so that term
+            // is added; 1/f'^2 comes from the shared reciprocal, since
+            // d = f'^2 (1 + O(h)).
+            const double q0 = d1 * r, q1 = d0 * r;
+            const double h0 = (f0 * g0) * q0, h1 = (f1 * g1) * q1;
+            const double e0 = fma(-m0, m0, g0) * q0, e1 = fma(-m1, m1, g1) * q1;
+            // x - h + e h^3 = x - h (1 - e h^2)
+            x0 = fma(-h0, fma(-(e0 * h0), h0, 1.0), x0);
+            x1 = fma(-h1, fma(-(e1 * h1), h1, 1.0), x1);
+            if (!__any(__builtin_fabsf(rf) > 1.0f - kNearDegenerate)) {
+                l0 = x0;
+                l1 = x1;
+                l2 = (tr - l0) - l1;
+                return;
+            }
         } else {
             const double h0 = (f0 * g0) * (d1 * r), h1 = (f1 * g1) * (d0 * r);
             x0 -= h0;

@@ -54,6 +54,15 @@ def eigen_spread_gap(p, A, anti):
     return lam[:, 2] - lam[:, 0], np.min(np.diff(lam, axis=1), axis=1)
 
 
+def fp64_bound(p, L, rho, ye, e, f):
+    """The FP64 tier's per-event error bound (module docstring)."""
+    anti = (f >> 4) & 1
+    A = oracle.k_matter() * ye * rho * e * np.where(anti == 1, -1.0, 1.0)
+    spread, gap = eigen_spread_gap(p, A, anti)
+    phase = oracle.k_phase() * spread * L / e
+    return 1e-12 + 4 * U53 * phase * (1.0 + spread / gap) + U53 * np.abs(A) / gap
+
+
 @pytest.mark.parametrize("seed", [7, 11])
 def test_random_configurations_within_bound(osc, ctx, seed):
     rng = np.random.default_rng(seed)
@@ -75,15 +84,53 @@ def test_random_configurations_within_bound(osc, ctx, seed):
         ctx.osc_reweight(ds, 0, out)
         got = out.cpu().numpy()
         want = oracle.prob_batch(p, L, rho, ye, e, f)
-        anti = (f >> 4) & 1
-        A = oracle.k_matter() * ye * rho * e * np.where(anti == 1, -1.0, 1.0)
-        spread, gap = eigen_spread_gap(p, A, anti)
-        phase = oracle.k_phase() * spread * L / e
-        bound = 1e-12 + 4 * U53 * phase * (1.0 + spread / gap) + U53 * np.abs(A) / gap
-        ratio = np.abs(got - want) / bound
+        ratio = np.abs(got - want) / fp64_bound(p, L, rho, ye, e, f)
         assert ratio.max() <= 1.0, (k, p, L, rho, float(ratio.max()))
         worst = max(worst, float(ratio.max()))
     print(f"worst error / bound over 60 configurations: {worst:.3g}")
+
+
+def test_near_level_crossings_within_bound(osc, ctx):
+    """Matter terms where two eigenvalues come within 0.1-3 % of the
+    spread (level crossings of sets with arbitrary angles, and large |A|
+    for near-measured sets): there the FP32 seeds are coarsest relative to
+    the smallest root distance, and below about 0.85 % the roots need
+    their second refinement step.  Such matter terms are found on a fine
+    grid of A, events are drawn around them and sorted by A (so that waves
+    fall on either side of that threshold, and near it), and every event
+    must stay within the FP64 bound, at a short baseline (small phases, so
+    the bound is about 1e-12) and a long one."""
+    rng = np.random.default_rng(21)
+    rho, ye = 13.0, 0.5
+    ka = oracle.k_matter() * ye * rho
+    sets = ([(workload.make_random_physics_sets(1, sd)[0], 0.1)
+             for sd in (1050, 1079, 31, 33, 35, 40, 44, 47)]
+            + [(workload.make_param_sets(1, sd)[0], 1.0) for sd in (35, 36)])
+    n = 20_000
+    checked = 0
+    for p, a_max in sets:
+        grid = np.linspace(-a_max, a_max, 100_001)
+        grid = grid[grid != 0.0]
+        spread, gap = eigen_spread_gap(p, grid, (grid < 0).astype(np.int64))
+        band = grid[(gap / spread >= 1e-3) & (gap / spread <= 3e-2)]
+        if band.size == 0:
+            continue
+        step = grid[1] - grid[0]
+        A = np.sort(rng.choice(band, n) + rng.uniform(-0.5, 0.5, n) * step)
+        e = np.abs(A) / ka
+        f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), A < 0)
+        for L in (300.0, 6000.0):
+            s = workload.Sample(e, f, np.ones(n), e.copy(), L_km=L, rho_gcc=rho, Ye=ye)
+            ctx.osc_set_params([p])
+            ds = osc.DeviceSample.from_host(s)
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            ctx.osc_reweight(ds, 0, out)
+            got = out.cpu().numpy()
+            want = oracle.prob_batch(p, L, rho, ye, e, f)
+            ratio = np.abs(got - want) / fp64_bound(p, L, rho, ye, e, f)
+            assert ratio.max() <= 1.0, (p, L, float(ratio.max()))
+        checked += 1
+    assert checked == len(sets)
 
 
 def test_mixed_tier_envelope(osc, ctx):
