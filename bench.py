@@ -39,27 +39,27 @@ HBM_PEAK_GBS = 8000.0
 SETTLE_S = 0.1   # untimed load before the warm-up steps (clock settle)
 # Algorithmic FP64 flops per event of the formulation the kernel follows
 # (an FMA counts two, a reciprocal estimate one): matter term and amplitude
-# inputs 9, cubic coefficients 12, trigonometric seeds (scaling in FP64) 6,
-# one Halley step with its third-order correction on two roots 56, third
-# root 2,
+# inputs 9, cubic coefficients 12 (the trigonometric seeds are FP32), one
+# Halley step with its third-order correction on two roots 54, third root 2,
 # differences, 1/(E Q) and the phase scale 16, coefficients of the
 # projectors X1 and X2 6, two sin and cos - 1 of the phase differences 52
 # (the phase products sit inside their reduction FMAs), numerators of X1
 # and X2 16, amplitude sum 15, |S|^2 3, weighted add 2 (w * P and the add
 # into the histogram).  Computing the bin per call adds 4 (scale, offset,
-# quotient, floor).  Waves with a matter term above 0.05 eV^2 add a Newton
-# step (30); the benchmark workloads stay below it.
-FLOPS_PER_EVENT = 195
-FLOPS_PER_EVENT_COMPUTED_BINS = 199
+# quotient, floor).  A wave in which two eigenvalues lie within ~0.85 % of
+# their spread adds a Newton step (31); no wave of the benchmark workloads
+# does.
+FLOPS_PER_EVENT = 187
+FLOPS_PER_EVENT_COMPUTED_BINS = 191
 # Layered path, per layer: matter term 1, cubic coefficients 9 and its
-# solution 67 (as above: p 3, seeds 6, corrected Halley 56, third root 2),
+# solution 59 (as above: p 3, corrected Halley 54, third root 2),
 # differences and 1/Q 12, phase scale 1, two sin and cos - 1 52, cos 2,
 # c_k 7, eigenvalue sums and products 6, polynomial coefficients a2, a1, a0
-# 19, y = M v 74, z = M y 74, v = a2 z + a1 y + a0 v 66: 390.  The first
+# 19, y = M v 74, z = M y 74, v = a2 z + a1 y + a0 v 66: 382.  The first
 # layer forms y as column alpha of M (2 instead of 74), the last only
 # component beta of z and v (26 + 22 instead of 74 + 66); per event 1/E 7,
 # |v_beta|^2 3 and the weighted add 2.
-LAYER_FLOPS = 390
+LAYER_FLOPS = 382
 
 
 def layered_flops_per_event(n_layers):
@@ -81,12 +81,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 92830.9, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 82528.3, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
-    "valu_per_event": 173.3,
-    "classes_per_event": {"fp64": 123.5, "fp64_trans": 2.0, "fp32": 12.0, "fp32_trans": 4.0,
-                          "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 19.75},
-    "source_sha256": "64d824135a6e81f7b49670b6ab6e44cece5fa85d77a6f0610b0ce3dba97218bf",
+    "fetch_kib": 92832.7, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 82554.0, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "valu_per_event": 169.9,
+    "classes_per_event": {"fp64": 119.5, "fp64_trans": 2.0, "fp32": 15.0, "fp32_trans": 4.0,
+                          "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 17.38},
+    "source_sha256": "e849e70ffb64b56cb6ce8c0a291e6e807649078495b740f49ee85c400f1c8757",
 }
 # Issue time of one wave instruction on one SIMD, measured on the box with
 # probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32

@@ -48,16 +48,20 @@ __device__ __forceinline__ double flip_sign(double v, uint32_t sign_bit)
     return __hiloint2double(__double2hiint(v) ^ int(sign_bit), __double2loint(v));
 }
 
+// p7 and q6 are kP7 and kQ6; a caller that evaluates many phases passes
+// them from VGPRs (see PolyRegs), so that each polynomial step reads at most
+// one constant from an SGPR pair (the VALU reads one per instruction).
 __device__ __forceinline__ void phase_sincos(double a, double b, const SinCosL* __restrict__ table,
-                                             double& sn, double& cm1)
+                                             double& sn, double& cm1, double p7 = kP7,
+                                             double q6 = kQ6)
 {
     const double t = __builtin_fma(a, b, kRoundMagic);
     const double n = t - kRoundMagic;
     const double u = __builtin_fma(a, b, -n);
     const SinCosL k = table[__double2loint(t) & 63];
     const double z = u * u;
-    const double s = u * __builtin_fma(z, __builtin_fma(z, __builtin_fma(z, kP7, kP5), kP3), kStep);
-    const double cm = z * __builtin_fma(z, __builtin_fma(z, kQ6, kQ4), kQ2);
+    const double s = u * __builtin_fma(z, __builtin_fma(z, __builtin_fma(z, p7, kP5), kP3), kStep);
+    const double cm = z * __builtin_fma(z, __builtin_fma(z, q6, kQ4), kQ2);
     sn = __builtin_fma(k.s, cm, __builtin_fma(k.c, s, k.s));
     cm1 = __builtin_fma(k.c, cm, __builtin_fma(-k.s, s, k.cm1));
 }
@@ -129,6 +133,25 @@ __device__ __forceinline__ double sgpr_value(double v)
     return v;
 }
 
+// The same, kept in a VGPR: loop-invariant operands that would otherwise
+// be the second SGPR operand of an instruction (and be copied into a VGPR
+// on every use).
+__device__ __forceinline__ double vgpr_value(double v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
+// The innermost sine and cosine coefficients of phase_sincos, which a
+// kernel that evaluates many phases loads into VGPRs once.
+struct PolyRegs {
+    double p7 = kP7, q6 = kQ6;
+    static __device__ __forceinline__ PolyRegs in_vgprs()
+    {
+        return PolyRegs{vgpr_value(kP7), vgpr_value(kQ6)};
+    }
+};
+
 // Roots of f(x) = x^3 - tr x^2 + c1 x - det (three real roots: the matrix
 // is Hermitian).  Two roots are seeded in FP32 from the trigonometric
 // solution x = tr/3 + (2/3) sqrt(p) cos(theta - 2 pi k / 3),
@@ -167,20 +190,21 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
     rf = __builtin_fminf(1.0f, __builtin_fmaxf(-1.0f, rf));
     // theta in revolutions for the hardware cosine: acos(r) / (3 * 2 pi)
     const float th = acos_seed_rev(rf);
-    const double k = double((2.0f / 3.0f) * (pf * rs));
-    const double t3 = tr * (1.0 / 3.0);
-    double x0 = fma(k, double(__builtin_amdgcn_cosf(th)), t3);
-    double x1 = fma(k, double(__builtin_amdgcn_cosf(th - 0.33333333f)), t3);
-    const double tr2 = 2.0 * tr;
+    // the seeds in FP32 (their FP32 rounding, ~6e-8 of |x|, is far below
+    // their error of ~1e-4 of the roots' spread)
+    const float kf = (2.0f / 3.0f) * (pf * rs);
+    const float t3f = float(tr) * (1.0f / 3.0f);
+    double x0 = double(__builtin_fmaf(kf, __builtin_amdgcn_cosf(th), t3f));
+    double x1 = double(__builtin_fmaf(kf, __builtin_amdgcn_cosf(th - 0.33333333f), t3f));
     const double three = sgpr_value(3.0);
     // Halley: x -= 2 f f' / (2 f'^2 - f f'')
     {
         const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
         const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
-        const double g0 = fma(x0, fma(three, x0, -tr2), c1);
-        const double g1 = fma(x1, fma(three, x1, -tr2), c1);
-        // -f f''/2 = f (tr - 3x)
+        // m = tr - 3x = -f''/2, and f' = x (3x - 2 tr) + c1 = c1 - x (m + tr)
         const double m0 = fma(-three, x0, tr), m1 = fma(-three, x1, tr);
+        const double g0 = fma(-x0, m0 + tr, c1);
+        const double g1 = fma(-x1, m1 + tr, c1);
         const double d0 = fma(g0, g0, f0 * m0);
         const double d1 = fma(g1, g1, f1 * m1);
         const double r = recip_coarse(d0 * d1);
@@ -222,6 +246,7 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
     }
     // Newton: x -= f / f'
     {
+        const double tr2 = 2.0 * tr;
         const double f0 = fma(fma(x0 - tr, x0, c1), x0, -det);
         const double f1 = fma(fma(x1 - tr, x1, c1), x1, -det);
         const double g0 = fma(x0, fma(three, x0, -tr2), c1);
@@ -242,7 +267,8 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
 // are formed.
 template <bool MIXED>
 __device__ __forceinline__ double event_prob(const SetConsts& sc, const Tables<MIXED>& T,
-                                             double kA, double kL, double E, uint32_t f)
+                                             double kA, double kL, double E, uint32_t f,
+                                             const PolyRegs& pr = PolyRegs{})
 {
     using Entry = std::conditional_t<MIXED, ChanF, ChanL>;
     using Real = std::conditional_t<MIXED, float, double>;
@@ -290,8 +316,8 @@ __device__ __forceinline__ double event_prob(const SetConsts& sc, const Tables<M
     double P;
     if constexpr (!MIXED) {
         double s1, e1, s2, e2;                        // sin and cos - 1
-        phase_sincos(-d01, ph, T.sct, s1, e1);        // phi_1 - phi_0
-        phase_sincos(-d02, ph, T.sct, s2, e2);        // phi_2 - phi_0
+        phase_sincos(-d01, ph, T.sct, s1, e1, pr.p7, pr.q6);   // phi_1 - phi_0
+        phase_sincos(-d02, ph, T.sct, s2, e2, pr.p7, pr.q6);   // phi_2 - phi_0
         const double x1r = fma(v1, dba, fma(-u1, mre, m2re)) * iD1;
         const double x1i = fma(-u1, mim, m2im) * iD1;
         const double x2r = fma(v2, dba, fma(-u2, mre, m2re)) * iD2;
@@ -348,9 +374,10 @@ struct ConstDensityProb {
     const SetConsts* sc;
     const Tables<MIXED>* tabs;
     double kA, kL;
+    PolyRegs pr;
     __device__ __forceinline__ double operator()(double E, uint32_t f) const
     {
-        return event_prob<MIXED>(*sc, *tabs, kA, kL, E, f);
+        return event_prob<MIXED>(*sc, *tabs, kA, kL, E, f, pr);
     }
 };
 

@@ -51,7 +51,8 @@ void tile_kernel(
     if (MODE != kReweight) hist_zero(hist, lane, nbt);
     __syncthreads();
 
-    const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL};
+    const ConstDensityProb<MIXED> prob{&sc, &tabs, pc.kA, pc.kL,
+                                       MIXED ? PolyRegs{} : PolyRegs::in_vgprs()};
     const TileArrays t = tile_arrays(tile, n, e_true, flags, weight, e_reco, bins, value, p_out);
     if (t.n == kTileEvents)
         tile_events<MODE, WRITE_P, true, WRITE_P>(prob, bc, hist, lane, t.n, t.e_true, t.flags,
