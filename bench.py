@@ -117,7 +117,11 @@ def valu_issue(kernel_ms, flops_per_event):
     issue_ms = ns * wave_events * 1e-6
     clock = (4 / (ISSUE_NS["fp64"] * 1e-9)) / CLOCK_HZ
     mix = (flops_per_event / 2 * ISSUE_NS["fp64"]) / ns
+    # FP64 VALU instructions per second against the FP64 pipe's instruction
+    # peak (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s)
+    fp64_lane_ops = (cls["fp64"] + cls["fp64_trans"]) * N_EVENTS / (kernel_ms * 1e-3)
     return {"valu_insts_per_event": COUNTER_TRAFFIC["valu_per_event"],
+            "fp64_pipe_frac": fp64_lane_ops / (FP64_PEAK_TFLOPS * 1e12 / 2),
             "classes_per_event": cls, "issue_ns_per_wave_event": ns,
             "issue_ms_at_measured_rates": issue_ms, "frac": issue_ms / kernel_ms,
             "decomposition": {"clock": clock, "mix": mix, "issue": issue_ms / kernel_ms,
