@@ -81,12 +81,12 @@ KERNEL_SOURCES = ("paper_1311_7579_amd/csrc/osc_device.h",
                   "paper_1311_7579_amd/csrc/osc_kernels.hip",
                   "paper_1311_7579_amd/build.py")
 COUNTER_TRAFFIC = {
-    "fetch_kib": 92832.7, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
-    "write_kib": 82554.0, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
-    "valu_per_event": 169.9,
+    "fetch_kib": 92836.0, "fetch_scale": 2.0,     # copy of 512 MiB: FETCH_SIZE 262157 KiB
+    "write_kib": 82562.4, "write_scale": 1.0,     # copy of 512 MiB: WRITE_SIZE 524288 KiB
+    "valu_per_event": 170.0,
     "classes_per_event": {"fp64": 119.5, "fp64_trans": 2.0, "fp32": 15.0, "fp32_trans": 4.0,
-                          "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 17.38},
-    "source_sha256": "e849e70ffb64b56cb6ce8c0a291e6e807649078495b740f49ee85c400f1c8757",
+                          "cvt": 5.0, "int32": 6.69, "int64": 0.375, "other": 17.44},
+    "source_sha256": "bda247f22a1b7708bb86df22b451d9748abe6d2a1e6e26a4b6f78e769d704574",
 }
 # Issue time of one wave instruction on one SIMD, measured on the box with
 # probe kernels of independent chains (ns): FP64 FMA/MUL/ADD 2.08, FP32

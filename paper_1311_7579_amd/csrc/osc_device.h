@@ -175,6 +175,13 @@ struct PolyRegs {
 // assembly resolves, and the phases stay within ~1e-8 rad up to 1e3 rad.
 constexpr double kHalleyOnly = 0x1p-12;
 constexpr float kNearDegenerate = 0x1p-12f;
+// Two roots closer than about 7e-4 of the spread (1 - |r| below this, near
+// an exact level crossing, which needs a zero mixing angle) round r to
+// within a few ulp of +-1 in FP32: both seeds then start from the pair's
+// midpoint, where f' vanishes, and no refinement separates them.  Such a
+// lane's P is undefined and comes out NaN (every such lane takes the
+// Newton step, where this is applied).
+constexpr float kUnresolved = 0x1p-19f;
 // FP32-mixed tier: waves with a matter term above this (eV^2, about 4
 // times the largest vacuum splitting) assemble the amplitude in FP64.
 constexpr double kMixedWideA = 0.01;
@@ -254,6 +261,7 @@ __device__ __forceinline__ void cubic_roots(double tr, double c1, double det, do
         const double r = recip_coarse(g0 * g1);
         x0 -= f0 * (g1 * r);
         x1 -= f1 * (g0 * r);
+        if (__builtin_fabsf(rf) > 1.0f - kUnresolved) x0 = __builtin_nan("");
     }
     l0 = x0;
     l1 = x1;

@@ -133,6 +133,85 @@ def test_near_level_crossings_within_bound(osc, ctx):
     assert checked == len(sets)
 
 
+def brute_force_prob(p, L, rho, ye, e, f):
+    """P from an eigendecomposition of the flavour-basis matrix (numpy
+    eigh, accurate however close the eigenvalues are)."""
+    anti = (f >> 4) & 1
+    a, b = f & 3, (f >> 2) & 3
+    out = np.empty(e.size)
+    m2 = np.array([0.0, p["dm2_21"], p["dm2_21"] + p["dm2_32"]])
+    for s in (0, 1):
+        sel = np.nonzero(anti == s)[0]
+        if sel.size == 0:
+            continue
+        U = oracle.pmns(p, anti=bool(s))
+        H = (U * m2) @ U.conj().T
+        M = np.broadcast_to(H, (sel.size, 3, 3)).copy()
+        M[:, 0, 0] += oracle.k_matter() * ye * rho * e[sel] * (-1.0 if s else 1.0)
+        lam, V = np.linalg.eigh(M)
+        ph = np.exp(-1j * oracle.k_phase() * L * lam / e[sel][:, None])
+        amp = np.einsum("nk,nk,nk->n", V[np.arange(sel.size), b[sel], :], ph,
+                        V[np.arange(sel.size), a[sel], :].conj())
+        out[sel] = np.abs(amp) ** 2
+    return out
+
+
+@pytest.mark.parametrize("angles", [(0.0, 0.311), (0.0251, 0.0)], ids=["th13=0", "th12=0"])
+def test_exact_level_crossings(osc, ctx, angles):
+    """A zero mixing angle decouples a mass state from nu_e, and its
+    eigenvalue then crosses another one exactly at one matter term.  The
+    analytic method cannot resolve eigenvalues that close (the oracle, which
+    follows it, gives NaN or errors up to ~1e-3 there), so the reference is
+    a brute-force eigendecomposition.  Events are drawn at relative
+    distances 1e-12..1e-1 from the crossing: the FP64 and layered paths give
+    NaN only where the two closest eigenvalues are within 1e-3 of the
+    spread, and elsewhere stay within the stated bound; the FP32-mixed tier
+    gives NaN on the same events and stays within 3e-4 elsewhere (its FP32
+    projector numerators cancel next to a crossing)."""
+    s13, s12 = angles
+    p = dict(workload.TABLE1, sin2_th13=s13, sin2_th12=s12)
+    rho, ye = 13.0, 0.5
+    grid = np.linspace(1e-5, 0.05, 400_001)
+    spread_g, gap_g = eigen_spread_gap(p, grid, np.zeros(grid.size, dtype=np.int64))
+    a_cross = grid[int(np.argmin(gap_g / spread_g))]
+    rng = np.random.default_rng(13)
+    n = 20_000
+    A = np.sort(a_cross * (1 + 10 ** rng.uniform(-12, -1, n) * np.where(rng.random(n) < 0.5, -1, 1)))
+    e = A / (oracle.k_matter() * ye * rho)
+    f = workload.make_flags(rng.integers(0, 3, n), rng.integers(0, 3, n), np.zeros(n, bool))
+    spread, gap = eigen_spread_gap(p, A, np.zeros(n, dtype=np.int64))
+    ctx.osc_set_params([p])
+    try:
+        for L in (300.0, 6000.0):
+            s = workload.Sample(e, f, np.ones(n), e.copy(), L_km=L, rho_gcc=rho, Ye=ye)
+            ds = osc.DeviceSample.from_host(s)
+            want = brute_force_prob(p, L, rho, ye, e, f)
+            bound = fp64_bound(p, L, rho, ye, e, f)
+            h = torch.empty(52, dtype=torch.float64, device="cuda")
+            results = {}
+            for tier in ("fp64", "layered", "mixed"):
+                out = torch.empty(n, dtype=torch.float64, device="cuda")
+                if tier == "fp64":
+                    ctx.osc_reweight(ds, 0, out)
+                elif tier == "layered":
+                    ctx.osc_reweight_layered(ds, [(L, rho, ye)], 0, out)
+                else:
+                    ctx.osc_fill_pdf(ds, 0, 50, 0.0, 3.0, h, out, precision=osc.OSC_FP32_MIXED)
+                results[tier] = out.cpu().numpy()
+            nan = np.isnan(results["fp64"])
+            assert nan.any() and (~nan).any()
+            assert (gap / spread)[nan].max() < 1e-3, (L, float((gap / spread)[nan].max()))
+            for tier, got in results.items():
+                np.testing.assert_array_equal(np.isnan(got), nan, err_msg=tier)
+                d = np.abs(got[~nan] - want[~nan])
+                if tier == "mixed":
+                    assert d.max() <= 3e-4, (L, tier, float(d.max()))
+                else:
+                    assert (d / bound[~nan]).max() <= 1.0, (L, tier, float((d / bound[~nan]).max()))
+    finally:
+        ctx.osc_set_params([workload.TABLE1])
+
+
 def test_mixed_tier_envelope(osc, ctx):
     """The FP32-mixed tier over the same random domain stays within the
     envelope the header states: about 5e-5 at worst (arbitrary angles,
