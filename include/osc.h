@@ -154,12 +154,13 @@ osc_status osc_validate_sample(osc_ctx* ctx, const osc_sample* sample, int64_t* 
  * the FP32 seeds of the eigenvalue solver can no longer resolve the two
  * roots that stay near the vacuum masses and P is not reliable.
  * Exact level crossings: with a zero mixing angle a mass state decouples
- * from nu_e and two eigenvalues cross at one matter term.  Events whose
- * two closest eigenvalues lie within about 7e-4 of the spread there (a
- * window of about +-7e-4 of the crossing energy for the atmospheric
- * crossing with sin2_th13 = 0, +-2 % for the solar one with
- * sin2_th12 = 0) cannot be resolved from the characteristic cubic; their
- * P is NaN, in both precision tiers and on layered paths.  Farther from the crossing the statement above holds
+ * from nu_e and two eigenvalues cross at one matter term (with a very
+ * small angle they nearly do).  Events whose two closest eigenvalues lie
+ * within about 7e-4 of the spread (next to the atmospheric crossing with
+ * sin2_th13 = 0, a window of about +-7e-4 of its energy; next to the solar
+ * one with sin2_th12 = 0, +-2 %) cannot be resolved from the
+ * characteristic cubic; their P is NaN, in both precision tiers and on
+ * layered paths.  Farther from the crossing the statement above holds
  * (the FP32-mixed tier: within 3e-4). */
 osc_status osc_reweight(osc_ctx* ctx, const osc_sample* sample, int32_t set,
                         double* p_out, void* stream);
